@@ -1,0 +1,271 @@
+"""Plain CPU oracle (test infrastructure only).
+
+A thin ctypes binding over ``sgm_oracle.c``: dense numpy arrays in, dense
+numpy arrays out, double precision for every floating-point quantity.  Only
+the tests, ``__graft_entry__.smoke()`` and the benchmark's CPU-baseline leg
+use it; the GPU library never does.
+
+Flags returned by :func:`predict` (per pixel of a predicted frame):
+``PRED`` a prediction exists, ``RESET`` the previous frame forced a full
+search, ``FULLWIN`` the window is [0, D-1].
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+import threading
+from typing import Optional
+
+import numpy as np
+
+__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "correct",
+           "OracleFilter", "PRED", "RESET", "FULLWIN", "PATH_DX", "PATH_DY"]
+
+PRED, RESET, FULLWIN = 1, 2, 4
+# path k has direction r = (PATH_DX[k], PATH_DY[k]); the predecessor of p is p - r
+PATH_DX = (+1, -1, 0, 0, +1, -1, -1, +1)
+PATH_DY = (0, 0, +1, -1, +1, -1, +1, -1)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sgm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction) into oracle/liboracle.so."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
+                    "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _CParams(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_disp", ctypes.c_int32),
+                ("census_w", ctypes.c_int32), ("census_h", ctypes.c_int32), ("path_mask", ctypes.c_uint32),
+                ("p1", ctypes.c_int32), ("p2", ctypes.c_int32),
+                ("k_sigma", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
+                ("chi2_gate", ctypes.c_double), ("disc_thresh", ctypes.c_double),
+                ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("baseline", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class Params:
+    """Method parameters (same fields and meaning as the GPU library's)."""
+    width: int
+    height: int
+    max_disp: int
+    census_w: int = 9
+    census_h: int = 7
+    path_mask: int = 0xFF
+    p1: int = 7
+    p2: int = 86
+    k_sigma: float = 3.0
+    q: float = 0.5
+    r: float = 1.0
+    chi2_gate: float = 6.634896601021214   # chi^2 with 1 dof, 99 %
+    disc_thresh: float = 2.0
+    f: float = 350.0
+    cx: Optional[float] = None
+    cy: Optional[float] = None
+    baseline: float = 0.54
+
+    def __post_init__(self):
+        if self.cx is None:
+            self.cx = (self.width - 1) / 2.0
+        if self.cy is None:
+            self.cy = (self.height - 1) / 2.0
+
+    @property
+    def nbits(self) -> int:
+        return self.census_w * self.census_h - 1
+
+    def c(self) -> _CParams:
+        return _CParams(self.width, self.height, self.max_disp, self.census_w, self.census_h,
+                        self.path_mask, self.p1, self.p2, self.k_sigma, self.q, self.r, self.chi2_gate,
+                        self.disc_thresh, self.f, self.cx, self.cy, self.baseline)
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            P = ctypes.c_void_p
+            i = ctypes.c_int
+            lib.orc_census.argtypes = [P, i, i, i, i, P]
+            lib.orc_cost.argtypes = [P, P, i, i, i, i, P, P, P]
+            lib.orc_aggregate.argtypes = [P, i, i, i, P, P, i, i, ctypes.c_uint, P, P]
+            lib.orc_wta.argtypes = [P, i, i, i, P, P, P, P]
+            lib.orc_match.argtypes = [P, P, P, P, P, P, P, P, P]
+            lib.orc_predict.argtypes = [P, P, P, P, P, P, P, P, P, P]
+            lib.orc_correct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
+            lib.orc_full_frame.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
+            lib.orc_reduced_frame.argtypes = [P] + [P] * 14
+            for name in ("orc_census", "orc_cost", "orc_aggregate", "orc_wta", "orc_match", "orc_predict",
+                         "orc_correct", "orc_full_frame", "orc_reduced_frame"):
+                getattr(lib, name).restype = ctypes.c_int
+            _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with code {rc}")
+
+
+def census(img: np.ndarray, cw: int = 9, ch: int = 7) -> np.ndarray:
+    img = _c(img, np.uint8)
+    H, W = img.shape
+    out = np.zeros((H, W), np.uint64)
+    _check(_load().orc_census(_p(img), W, H, cw, ch, _p(out)), "census")
+    return out
+
+
+def cost(cl: np.ndarray, cr: np.ndarray, D: int, nbits: int, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
+    """Dense [H, W, D] int32 costs; cells outside [lo, hi] are -1."""
+    cl, cr = _c(cl, np.uint64), _c(cr, np.uint64)
+    lo, hi = _c(lo, np.int32), _c(hi, np.int32)
+    H, W = cl.shape
+    C = np.full((H, W, D), -1, np.int32)
+    _check(_load().orc_cost(_p(cl), _p(cr), W, H, D, nbits, _p(lo), _p(hi), _p(C)), "cost")
+    return C
+
+
+def aggregate(C: np.ndarray, lo: np.ndarray, hi: np.ndarray, p1: int, p2: int, path_mask: int = 0xFF,
+              want_lr: bool = False):
+    """S [H, W, D] int32 (and per-path L_r [8, H, W, D] if want_lr); -1 outside windows."""
+    C = _c(C, np.int32)
+    lo, hi = _c(lo, np.int32), _c(hi, np.int32)
+    H, W, D = C.shape
+    S = np.full((H, W, D), -1, np.int32)
+    Lr = np.full((8, H, W, D), -1, np.int32) if want_lr else None
+    _check(_load().orc_aggregate(_p(C), W, H, D, _p(lo), _p(hi), p1, p2, path_mask, _p(S), _p(Lr)),
+           "aggregate")
+    return (S, Lr) if want_lr else S
+
+
+def wta(S: np.ndarray, lo: np.ndarray, hi: np.ndarray):
+    S = _c(S, np.int32)
+    lo, hi = _c(lo, np.int32), _c(hi, np.int32)
+    H, W, D = S.shape
+    dstar = np.zeros((H, W), np.int32)
+    dz = np.zeros((H, W), np.float64)
+    _check(_load().orc_wta(_p(S), W, H, D, _p(lo), _p(hi), _p(dstar), _p(dz)), "wta")
+    return dstar, dz
+
+
+def match(prm: Params, left: np.ndarray, right: np.ndarray, lo: np.ndarray, hi: np.ndarray,
+          want_cs: bool = False):
+    """Census, cost, aggregation and WTA on the given windows -> (dstar, dz[, C, S])."""
+    left, right = _c(left, np.uint8), _c(right, np.uint8)
+    lo, hi = _c(lo, np.int32), _c(hi, np.int32)
+    H, W = left.shape
+    dstar = np.zeros((H, W), np.int32)
+    dz = np.zeros((H, W), np.float64)
+    C = np.full((H, W, prm.max_disp), -1, np.int32) if want_cs else None
+    S = np.full((H, W, prm.max_disp), -1, np.int32) if want_cs else None
+    cp = prm.c()
+    _check(_load().orc_match(ctypes.byref(cp), _p(left), _p(right), _p(lo), _p(hi), _p(dstar), _p(dz),
+                             _p(C), _p(S)), "match")
+    return (dstar, dz, C, S) if want_cs else (dstar, dz)
+
+
+def predict(prm: Params, d: np.ndarray, p: np.ndarray, sflags: np.ndarray, T: np.ndarray):
+    """Warp + hole fill + discontinuity rejection + windows -> (dhat, pm, flags, lo, hi)."""
+    d, p = _c(d, np.float64), _c(p, np.float64)
+    sflags = _c(sflags, np.uint8)
+    T = _c(T, np.float64).reshape(16)
+    H, W = d.shape
+    dhat = np.zeros((H, W), np.float64)
+    pm = np.zeros((H, W), np.float64)
+    flags = np.zeros((H, W), np.uint8)
+    lo = np.zeros((H, W), np.int32)
+    hi = np.zeros((H, W), np.int32)
+    cp = prm.c()
+    _check(_load().orc_predict(ctypes.byref(cp), _p(d), _p(p), _p(sflags), _p(T), _p(dhat), _p(pm),
+                               _p(flags), _p(lo), _p(hi)), "predict")
+    return dhat, pm, flags, lo, hi
+
+
+def correct(prm: Params, dhat, pm, flags, lo, hi, dstar, dz):
+    """Kalman correction + innovation test -> (d, p, mask, sflags)."""
+    dhat, pm, dz = _c(dhat, np.float64), _c(pm, np.float64), _c(dz, np.float64)
+    flags = _c(flags, np.uint8)
+    lo, hi, dstar = _c(lo, np.int32), _c(hi, np.int32), _c(dstar, np.int32)
+    H, W = dhat.shape
+    d = np.zeros((H, W), np.float64)
+    p = np.zeros((H, W), np.float64)
+    mask = np.zeros((H, W), np.uint8)
+    sflags = np.zeros((H, W), np.uint8)
+    cp = prm.c()
+    _check(_load().orc_correct(ctypes.byref(cp), _p(dhat), _p(pm), _p(flags), _p(lo), _p(hi), _p(dstar),
+                               _p(dz), _p(d), _p(p), _p(mask), _p(sflags)), "correct")
+    return d, p, mask, sflags
+
+
+class OracleFilter:
+    """Frame-level driver: full_frame() once, then reduced_frame(T) per frame.
+
+    After each call the attributes hold the frame's results: d, p (state),
+    sflags (RESET for the next frame), mask (moving), lo, hi, dstar, dz and,
+    for reduced frames, dhat, pm, flags.
+    """
+
+    def __init__(self, prm: Params):
+        self.prm = prm
+        H, W = prm.height, prm.width
+        self.d = np.zeros((H, W), np.float64)
+        self.p = np.zeros((H, W), np.float64)
+        self.sflags = np.zeros((H, W), np.uint8)
+        self.mask = np.zeros((H, W), np.uint8)
+        self.lo = np.zeros((H, W), np.int32)
+        self.hi = np.zeros((H, W), np.int32)
+        self.dstar = np.zeros((H, W), np.int32)
+        self.dz = np.zeros((H, W), np.float64)
+        self.dhat = np.zeros((H, W), np.float64)
+        self.pm = np.zeros((H, W), np.float64)
+        self.flags = np.zeros((H, W), np.uint8)
+        self.started = False
+
+    def full_frame(self, left, right):
+        left, right = _c(left, np.uint8), _c(right, np.uint8)
+        cp = self.prm.c()
+        _check(_load().orc_full_frame(ctypes.byref(cp), _p(left), _p(right), _p(self.d), _p(self.p),
+                                      _p(self.sflags), _p(self.mask), _p(self.lo), _p(self.hi),
+                                      _p(self.dstar), _p(self.dz)), "full_frame")
+        self.flags[:] = FULLWIN
+        self.started = True
+
+    def reduced_frame(self, left, right, T):
+        if not self.started:
+            raise RuntimeError("reduced_frame before full_frame")
+        left, right = _c(left, np.uint8), _c(right, np.uint8)
+        T = _c(T, np.float64).reshape(16)
+        cp = self.prm.c()
+        _check(_load().orc_reduced_frame(ctypes.byref(cp), _p(left), _p(right), _p(T), _p(self.d),
+                                         _p(self.p), _p(self.sflags), _p(self.mask), _p(self.dhat),
+                                         _p(self.pm), _p(self.flags), _p(self.lo), _p(self.hi),
+                                         _p(self.dstar), _p(self.dz)), "reduced_frame")
+
+    def set_state(self, d, p, sflags):
+        self.d[:] = d
+        self.p[:] = p
+        self.sflags[:] = sflags
+        self.started = True

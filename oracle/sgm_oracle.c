@@ -1,0 +1,512 @@
+/*
+ * Plain CPU oracle for reduced-space SGM fused by a per-pixel Kalman filter
+ * (Popovic, Hadviger, Markovic, Petrovic, "Computationally efficient dense
+ * moving object detection based on reduced space disparity estimation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * statement of what the GPU path computes.  It shares no code, header, table
+ * or helper with the GPU library and is used only by the tests, the smoke
+ * check and the benchmark's CPU baseline.
+ *
+ * Dense storage, scalar loops, double precision for every floating-point
+ * quantity, one thread.  Each function names the passage of the paper it
+ * follows.  Where the paper is silent the reading used is stated at the
+ * function (the design notes list all of them).
+ *
+ * Build: gcc -O2 -std=c99 -ffp-contract=off -shared -fPIC (no FMA
+ * contraction, so every floating-point operation is one IEEE-754 rounding in
+ * the order written).
+ */
+#include "sgm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_INF 1000000000
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ------------------------------------------------------------------------
+ * Census transform (Section 2.1, "Matching cost calculation").
+ * Each pixel is described by comparing its neighbours inside a cw x ch
+ * window with the centre.  Reading of the unspecified details: bit = 1 when
+ * the neighbour is strictly darker than the centre; neighbours are visited in
+ * raster order (rows top to bottom, columns left to right) skipping the
+ * centre, and each new bit is shifted in at the least significant end, so the
+ * first neighbour ends in the most significant used bit; outside the image
+ * the nearest edge pixel is used.
+ * ---------------------------------------------------------------------- */
+int orc_census(const uint8_t *img, int W, int H, int cw, int ch, uint64_t *out)
+{
+    if (cw < 1 || ch < 1 || (cw % 2) == 0 || (ch % 2) == 0 || cw * ch - 1 > 64)
+        return -1;
+    int rx = cw / 2, ry = ch / 2;
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            uint8_t c = img[y * W + x];
+            uint64_t bits = 0;
+            for (int dy = -ry; dy <= ry; dy++) {
+                for (int dx = -rx; dx <= rx; dx++) {
+                    if (dx == 0 && dy == 0)
+                        continue;
+                    int yy = clampi(y + dy, 0, H - 1);
+                    int xx = clampi(x + dx, 0, W - 1);
+                    bits = (bits << 1) | (uint64_t)(img[yy * W + xx] < c ? 1 : 0);
+                }
+            }
+            out[y * W + x] = bits;
+        }
+    }
+    return 0;
+}
+
+static int popcount64(uint64_t v)
+{
+    int n = 0;
+    while (v) {
+        n += (int)(v & 1u);
+        v >>= 1;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------
+ * Matching cost (Section 2.1): Hamming distance between the left census at
+ * (x, y) and the right census at (x - d, y).  Reading: when x - d < 0 the
+ * match is outside the right image and gets the largest possible cost, the
+ * number of census bits.  Only cells inside the pixel's window [lo, hi] are
+ * computed (the reduced search space of Section 2); C is dense [H][W][D] and
+ * cells outside the window are left untouched.
+ * ---------------------------------------------------------------------- */
+int orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int nbits,
+             const int32_t *lo, const int32_t *hi, int32_t *C)
+{
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            int p = y * W + x;
+            for (int d = lo[p]; d <= hi[p]; d++) {
+                int32_t c;
+                if (x - d < 0)
+                    c = nbits;
+                else
+                    c = popcount64(cl[p] ^ cr[y * W + (x - d)]);
+                C[(size_t)p * D + d] = c;
+            }
+        }
+    }
+    return 0;
+}
+
+/* Path directions r; the predecessor of p along r is p - r.  Reading of which
+ * four are "nondiagonal" (Table 2): the horizontal and vertical ones, bits
+ * 0..3 of the path mask; the diagonal ones are bits 4..7. */
+static const int PATH_DX[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
+static const int PATH_DY[8] = {0, 0, +1, -1, +1, -1, +1, -1};
+
+/* ------------------------------------------------------------------------
+ * Cost aggregation, Eq. (1) (Section 2.2), on per-pixel disparity windows.
+ *
+ *   L_r(p,d) = C(p,d) + min( L_r(p-r,d), L_r(p-r,d-1)+P1, L_r(p-r,d+1)+P1,
+ *                            min_i L_r(p-r,i)+P2 ) - min_i L_r(p-r,i)
+ *
+ * Readings: (a) the trailing subtraction of the predecessor's minimum is the
+ * usual normalisation that keeps the accumulated loss small enough for 16-bit
+ * integers (the paper stores it in 16 bits); it shifts every L_r(p,.) by the
+ * same amount and so changes no minimiser.  (b) With reduced search spaces
+ * the predecessor only has values inside its own window W_{p-r}; every term
+ * that refers to a disparity outside it is absent (+infinity), and the P2
+ * term's minimum runs over W_{p-r}.  (c) A pixel whose predecessor lies
+ * outside the image starts the path: L_r(p,d) = C(p,d).
+ * The sum over the selected paths is S(p,d) = sum_r L_r(p,d), for d in W_p.
+ * If Lr_out is not NULL, path k's L_r is stored at Lr_out[k][p][d].
+ * ---------------------------------------------------------------------- */
+int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+                  int p1, int p2, unsigned path_mask, int32_t *S, int32_t *Lr_out)
+{
+    size_t cells = (size_t)W * H * D;
+    int32_t *Lr = (int32_t *)malloc(cells * sizeof(int32_t));
+    if (!Lr)
+        return -2;
+    for (int y = 0; y < H; y++)
+        for (int x = 0; x < W; x++) {
+            int p = y * W + x;
+            for (int d = lo[p]; d <= hi[p]; d++)
+                S[(size_t)p * D + d] = 0;
+        }
+    for (int k = 0; k < 8; k++) {
+        if (!(path_mask & (1u << k)))
+            continue;
+        int rx = PATH_DX[k], ry = PATH_DY[k];
+        /* visit order: the predecessor p - r is always visited before p */
+        for (int iy = 0; iy < H; iy++) {
+            int y = (ry >= 0) ? iy : H - 1 - iy;
+            for (int ix = 0; ix < W; ix++) {
+                int x = (rx >= 0) ? ix : W - 1 - ix;
+                int p = y * W + x;
+                int qx = x - rx, qy = y - ry;
+                if (qx < 0 || qx >= W || qy < 0 || qy >= H) {
+                    for (int d = lo[p]; d <= hi[p]; d++)
+                        Lr[(size_t)p * D + d] = C[(size_t)p * D + d];
+                    continue;
+                }
+                int q = qy * W + qx;
+                int mq = ORC_INF;
+                for (int i = lo[q]; i <= hi[q]; i++)
+                    if (Lr[(size_t)q * D + i] < mq)
+                        mq = Lr[(size_t)q * D + i];
+                for (int d = lo[p]; d <= hi[p]; d++) {
+                    int best = mq + p2;
+                    if (d >= lo[q] && d <= hi[q] && Lr[(size_t)q * D + d] < best)
+                        best = Lr[(size_t)q * D + d];
+                    if (d - 1 >= lo[q] && d - 1 <= hi[q] && Lr[(size_t)q * D + d - 1] + p1 < best)
+                        best = Lr[(size_t)q * D + d - 1] + p1;
+                    if (d + 1 >= lo[q] && d + 1 <= hi[q] && Lr[(size_t)q * D + d + 1] + p1 < best)
+                        best = Lr[(size_t)q * D + d + 1] + p1;
+                    Lr[(size_t)p * D + d] = C[(size_t)p * D + d] + best - mq;
+                }
+            }
+        }
+        for (int y = 0; y < H; y++)
+            for (int x = 0; x < W; x++) {
+                int p = y * W + x;
+                for (int d = lo[p]; d <= hi[p]; d++) {
+                    S[(size_t)p * D + d] += Lr[(size_t)p * D + d];
+                    if (Lr_out)
+                        Lr_out[(size_t)k * cells + (size_t)p * D + d] = Lr[(size_t)p * D + d];
+                }
+            }
+    }
+    free(Lr);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Winner-takes-all (Section 2.3) with a parabolic sub-pixel fit.
+ * d* is the smallest disparity of the window attaining min_d S(p,d) (reading:
+ * ties go to the lower disparity).  When both d*-1 and d*+1 lie in the
+ * window, a parabola through the three sums gives the offset
+ * (a - b) / (2 (a + b)), a = S(d*-1)-S(d*) >= 1, b = S(d*+1)-S(d*) >= 0;
+ * otherwise the measurement is d* itself.
+ * ---------------------------------------------------------------------- */
+int orc_wta(const int32_t *S, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+            int32_t *dstar, double *dz)
+{
+    for (int p = 0; p < W * H; p++) {
+        const int32_t *s = S + (size_t)p * D;
+        int best = lo[p];
+        for (int d = lo[p] + 1; d <= hi[p]; d++)
+            if (s[d] < s[best])
+                best = d;
+        dstar[p] = best;
+        if (best - 1 >= lo[p] && best + 1 <= hi[p]) {
+            int a = s[best - 1] - s[best];
+            int b = s[best + 1] - s[best];
+            dz[p] = (double)best + (double)(a - b) / (double)(2 * (a + b));
+        } else {
+            dz[p] = (double)best;
+        }
+    }
+    return 0;
+}
+
+/* Full pipeline of the matcher on given windows: census, cost, aggregation,
+ * WTA.  C and S are dense [H][W][D] scratch owned by the caller (or NULL to
+ * let the oracle allocate them). */
+int orc_match(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+              const int32_t *lo, const int32_t *hi, int32_t *dstar, double *dz,
+              int32_t *C_out, int32_t *S_out)
+{
+    int W = prm->width, H = prm->height, D = prm->max_disp;
+    size_t n = (size_t)W * H, cells = n * D;
+    uint64_t *cl = (uint64_t *)malloc(n * sizeof(uint64_t));
+    uint64_t *cr = (uint64_t *)malloc(n * sizeof(uint64_t));
+    int32_t *C = C_out ? C_out : (int32_t *)malloc(cells * sizeof(int32_t));
+    int32_t *S = S_out ? S_out : (int32_t *)malloc(cells * sizeof(int32_t));
+    int rc = 0;
+    if (!cl || !cr || !C || !S) {
+        rc = -2;
+        goto done;
+    }
+    if (orc_census(left, W, H, prm->census_w, prm->census_h, cl) ||
+        orc_census(right, W, H, prm->census_w, prm->census_h, cr)) {
+        rc = -1;
+        goto done;
+    }
+    orc_cost(cl, cr, W, H, D, prm->census_w * prm->census_h - 1, lo, hi, C);
+    rc = orc_aggregate(C, W, H, D, lo, hi, prm->p1, prm->p2, prm->path_mask, S, NULL);
+    if (rc)
+        goto done;
+    orc_wta(S, W, H, D, lo, hi, dstar, dz);
+done:
+    free(cl);
+    free(cr);
+    if (!C_out)
+        free(C);
+    if (!S_out)
+        free(S);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Prediction (Section 2.4, Eq. 2-4) and the rules that follow it.
+ *
+ * Eq. (2) maps disparity-space points omega = (x, y, d) of frame k-1 into
+ * frame k with a 4x4 matrix.  Reading: the matrix is the ego-motion T
+ * (X_k = R X_{k-1} + t, metric camera coordinates) conjugated by the stereo
+ * projection, followed by the homogeneous division.  Written out with
+ * h = ((x-cx) B, (y-cy) B, f B) (= d * X):
+ *     h' = R h + t d,   x' = f h'_x / h'_z + cx,   y' = f h'_y / h'_z + cy,
+ *     d' = f B d / h'_z,   Phi = d' / d = f B / h'_z  (Eq. 3, defined at d=0),
+ *     p' = Phi^2 p + q   (Eq. 4).
+ * Readings: a source is dropped when h'_z <= 1e-9 f B (behind the camera),
+ * when its nearest target pixel floor(x'+0.5), floor(y'+0.5) is outside the
+ * image, or when d' > D-1.  Several sources landing on one target: the
+ * largest d' (nearest surface) wins, then the smallest source index y*W+x.
+ * The winner's RESET bit travels with it.
+ *
+ * Zooming holes (Section 2.4): a target without a winner that has known
+ * left and right neighbours, or known upper and lower neighbours, takes the
+ * mean disparity and the mean variance of those neighbours (all valid pairs:
+ * 2 or 4 values, summed in the order left, right, up, down).  Reading: one
+ * pass over the winners only; the RESET bits of the contributors are OR-ed.
+ *
+ * Discontinuities (Section 2.4): "reject the predicted disparities near
+ * disparity discontinuities".  Reading: on the filled map, a predicted pixel
+ * is rejected when a predicted pixel of its 8-neighbourhood differs by more
+ * than disc_thresh.  (Under forward motion the nearer surface spreads apart
+ * and occluded background lands in the one-pixel gaps of its splat; where a
+ * gap row crosses a gap column only the diagonal neighbours still show the
+ * nearer surface.)
+ *
+ * Search limits (Section 2.4): the paper writes d^{k|k-1} +- p^{k|k-1}.
+ * Reading: +- k_sigma standard deviations, rounded outward:
+ * lo = max(0, floor(dh - k sqrt(p))), hi = min(D-1, ceil(dh + k sqrt(p))).
+ * A pixel without a prediction, or with RESET, searches the whole range
+ * [0, D-1] (the initialisation of Section 2.4).
+ *
+ * Inputs: previous state d, p (double), sflags (ORC_RESET bit).
+ * Outputs: dhat, pm (double), flags (ORC_PRED | ORC_RESET | ORC_FULLWIN), lo, hi.
+ * ---------------------------------------------------------------------- */
+int orc_predict(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
+                const double T[16], double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi)
+{
+    int W = prm->width, H = prm->height, D = prm->max_disp;
+    size_t n = (size_t)W * H;
+    double f = prm->f, B = prm->baseline, cx = prm->cx, cy = prm->cy;
+    double fB = f * B;
+    int64_t *win = (int64_t *)malloc(n * sizeof(int64_t));   /* winning source per target */
+    double *dw = (double *)malloc(n * sizeof(double));
+    double *pw = (double *)malloc(n * sizeof(double));
+    uint8_t *rw = (uint8_t *)malloc(n);
+    uint8_t *has = (uint8_t *)malloc(n);
+    uint8_t *pred = (uint8_t *)malloc(n);
+    uint8_t *rst = (uint8_t *)malloc(n);
+    if (!win || !dw || !pw || !rw || !has || !pred || !rst) {
+        free(win); free(dw); free(pw); free(rw); free(has); free(pred); free(rst);
+        return -2;
+    }
+    for (size_t t = 0; t < n; t++) {
+        win[t] = -1;
+        dw[t] = 0.0;
+        pw[t] = 0.0;
+        rw[t] = 0;
+        has[t] = 0;
+    }
+    /* warp and z-buffer */
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            int s = y * W + x;
+            double X = ((double)x - cx) * B;
+            double Y = ((double)y - cy) * B;
+            double ds = d[s];
+            double hx = ((T[0] * X + T[1] * Y) + T[2] * fB) + T[3] * ds;
+            double hy = ((T[4] * X + T[5] * Y) + T[6] * fB) + T[7] * ds;
+            double hz = ((T[8] * X + T[9] * Y) + T[10] * fB) + T[11] * ds;
+            if (!(hz > 1e-9 * fB))
+                continue;
+            double xp = (f * hx) / hz + cx;
+            double yp = (f * hy) / hz + cy;
+            double dp = (fB * ds) / hz;
+            double phi = fB / hz;
+            double pp = (phi * phi) * p[s] + prm->q;
+            double ux = xp + 0.5, uy = yp + 0.5;
+            if (!(ux >= 0.0 && ux < (double)W && uy >= 0.0 && uy < (double)H))
+                continue;
+            if (!(dp <= (double)(D - 1)))
+                continue;
+            int tx = (int)floor(ux), ty = (int)floor(uy);
+            int t = ty * W + tx;
+            /* sources are visited in increasing index, so a strictly larger d'
+             * is needed to replace the current winner */
+            if (win[t] < 0 || dp > dw[t]) {
+                win[t] = s;
+                dw[t] = dp;
+                pw[t] = pp;
+                rw[t] = (uint8_t)(sflags[s] & ORC_RESET);
+            }
+        }
+    }
+    for (size_t t = 0; t < n; t++)
+        has[t] = win[t] >= 0;
+    /* zooming-hole fill from the winners */
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            int t = y * W + x;
+            pred[t] = has[t];
+            dhat[t] = dw[t];
+            pm[t] = pw[t];
+            rst[t] = rw[t];
+            if (has[t])
+                continue;
+            int hpair = x - 1 >= 0 && x + 1 < W && has[t - 1] && has[t + 1];
+            int vpair = y - 1 >= 0 && y + 1 < H && has[t - W] && has[t + W];
+            if (hpair && vpair) {
+                dhat[t] = (((dw[t - 1] + dw[t + 1]) + dw[t - W]) + dw[t + W]) / 4.0;
+                pm[t] = (((pw[t - 1] + pw[t + 1]) + pw[t - W]) + pw[t + W]) / 4.0;
+                rst[t] = rw[t - 1] | rw[t + 1] | rw[t - W] | rw[t + W];
+                pred[t] = 1;
+            } else if (hpair) {
+                dhat[t] = (dw[t - 1] + dw[t + 1]) / 2.0;
+                pm[t] = (pw[t - 1] + pw[t + 1]) / 2.0;
+                rst[t] = rw[t - 1] | rw[t + 1];
+                pred[t] = 1;
+            } else if (vpair) {
+                dhat[t] = (dw[t - W] + dw[t + W]) / 2.0;
+                pm[t] = (pw[t - W] + pw[t + W]) / 2.0;
+                rst[t] = rw[t - W] | rw[t + W];
+                pred[t] = 1;
+            }
+        }
+    }
+    /* discontinuity rejection, decided on the filled map before any pixel is
+     * rejected (has[] is reused to hold the verdict) */
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            int t = y * W + x;
+            int ok = pred[t];
+            if (ok) {
+                for (int yy = y - 1; yy <= y + 1; yy++) {
+                    for (int xx = x - 1; xx <= x + 1; xx++) {
+                        if (xx < 0 || xx >= W || yy < 0 || yy >= H || (xx == x && yy == y))
+                            continue;
+                        int u = yy * W + xx;
+                        if (pred[u] && fabs(dhat[t] - dhat[u]) > prm->disc_thresh)
+                            ok = 0;
+                    }
+                }
+            }
+            has[t] = (uint8_t)ok;
+        }
+    }
+    /* search limits */
+    for (size_t t = 0; t < n; t++) {
+        int ok = has[t];
+        uint8_t fl = 0;
+        if (ok)
+            fl |= ORC_PRED;
+        if (rst[t])
+            fl |= ORC_RESET;
+        int full = !ok || rst[t] || !(dhat[t] >= 0.0 && dhat[t] <= (double)(D - 1));
+        if (full) {
+            fl |= ORC_FULLWIN;
+            lo[t] = 0;
+            hi[t] = D - 1;
+        } else {
+            double s = sqrt(pm[t]);
+            double a = dhat[t] - prm->k_sigma * s;
+            double b = dhat[t] + prm->k_sigma * s;
+            int l = (int)floor(a), h = (int)ceil(b);
+            lo[t] = l < 0 ? 0 : l;
+            hi[t] = h > D - 1 ? D - 1 : h;
+        }
+        if (!ok) {
+            dhat[t] = 0.0;
+            pm[t] = 0.0;
+        }
+        flags[t] = fl;
+    }
+    free(win); free(dw); free(pw); free(rw); free(has); free(pred); free(rst);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------
+ * Correction (Section 2.4, Eq. 5-6) and the innovation test.
+ * K = p^- / (p^- + r) (reading: the gain the paper leaves unprinted is the
+ * optimal one); d = dh + K (dz - dh); p = (1-K)^2 p^- + K^2 r (Eq. 6).
+ * A pixel whose window was the full range (no prediction, or RESET) starts
+ * over from the measurement: d = dz, p = r (the initialisation of Section
+ * 2.4).
+ * Moving objects (Section 4) are where prediction and measurement disagree.
+ * Reading: a pixel with a prediction is marked moving when the normalised
+ * innovation nu^2 / (p^- + r) exceeds chi2_gate.  RESET for the next frame is
+ * set for moving pixels and for pixels whose minimum sat on an inner window
+ * edge (d* = lo > 0 or d* = hi < D-1).
+ * ---------------------------------------------------------------------- */
+int orc_correct(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
+                const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
+                double *d, double *p, uint8_t *mask, uint8_t *sflags)
+{
+    int n = prm->width * prm->height, D = prm->max_disp;
+    double r = prm->r;
+    for (int t = 0; t < n; t++) {
+        int moving = 0;
+        double nu = 0.0, S = 0.0;
+        if (flags[t] & ORC_PRED) {
+            nu = dz[t] - dhat[t];
+            S = pm[t] + r;
+            moving = (nu * nu) / S > prm->chi2_gate;
+        }
+        if (flags[t] & ORC_FULLWIN) {
+            d[t] = dz[t];
+            p[t] = r;
+        } else {
+            double K = pm[t] / S;
+            double a = 1.0 - K;
+            d[t] = dhat[t] + K * nu;
+            p[t] = (a * a) * pm[t] + (K * K) * r;
+        }
+        int sat = (dstar[t] == lo[t] && lo[t] > 0) || (dstar[t] == hi[t] && hi[t] < D - 1);
+        mask[t] = (uint8_t)moving;
+        sflags[t] = (uint8_t)((moving || sat) ? ORC_RESET : 0);
+    }
+    return 0;
+}
+
+/* Frame 0 (Section 2.4: limits initially cover the whole search space, which
+ * is conventional SGM): full windows, then d = dz, p = r, no motion. */
+int orc_full_frame(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+                   double *d, double *p, uint8_t *sflags, uint8_t *mask,
+                   int32_t *lo, int32_t *hi, int32_t *dstar, double *dz)
+{
+    int n = prm->width * prm->height;
+    for (int t = 0; t < n; t++) {
+        lo[t] = 0;
+        hi[t] = prm->max_disp - 1;
+    }
+    int rc = orc_match(prm, left, right, lo, hi, dstar, dz, NULL, NULL);
+    if (rc)
+        return rc;
+    for (int t = 0; t < n; t++) {
+        d[t] = dz[t];
+        p[t] = prm->r;
+        sflags[t] = 0;
+        mask[t] = 0;
+    }
+    return 0;
+}
+
+/* One steady-state frame: predict, match inside the windows, correct. */
+int orc_reduced_frame(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+                      const double T[16], double *d, double *p, uint8_t *sflags, uint8_t *mask,
+                      double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi,
+                      int32_t *dstar, double *dz)
+{
+    int rc = orc_predict(prm, d, p, sflags, T, dhat, pm, flags, lo, hi);
+    if (rc)
+        return rc;
+    rc = orc_match(prm, left, right, lo, hi, dstar, dz, NULL, NULL);
+    if (rc)
+        return rc;
+    return orc_correct(prm, dhat, pm, flags, lo, hi, dstar, dz, d, p, mask, sflags);
+}

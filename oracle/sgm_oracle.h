@@ -1,0 +1,56 @@
+/*
+ * Plain CPU oracle (test infrastructure only): reduced-space SGM fused by a
+ * per-pixel Kalman filter.  Host pointers, dense arrays, double precision for
+ * all floating-point state.  Used by the tests, the smoke check and the
+ * benchmark's CPU baseline; never by the GPU library.
+ */
+#ifndef SGM_ORACLE_H
+#define SGM_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* per-pixel flags of a predicted frame */
+#define ORC_PRED 1u     /* a prediction (warp winner or filled hole) survived */
+#define ORC_RESET 2u    /* full-range search forced by the previous frame */
+#define ORC_FULLWIN 4u  /* this frame searched [0, D-1] */
+
+typedef struct {
+    int32_t width, height, max_disp;
+    int32_t census_w, census_h;
+    uint32_t path_mask;
+    int32_t p1, p2;
+    double k_sigma, q, r, chi2_gate, disc_thresh;
+    double f, cx, cy, baseline;
+} orc_params;
+
+int orc_census(const uint8_t *img, int W, int H, int cw, int ch, uint64_t *out);
+int orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int nbits,
+             const int32_t *lo, const int32_t *hi, int32_t *C);
+int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+                  int p1, int p2, unsigned path_mask, int32_t *S, int32_t *Lr_out);
+int orc_wta(const int32_t *S, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+            int32_t *dstar, double *dz);
+int orc_match(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+              const int32_t *lo, const int32_t *hi, int32_t *dstar, double *dz,
+              int32_t *C_out, int32_t *S_out);
+int orc_predict(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
+                const double T[16], double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi);
+int orc_correct(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
+                const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
+                double *d, double *p, uint8_t *mask, uint8_t *sflags);
+int orc_full_frame(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+                   double *d, double *p, uint8_t *sflags, uint8_t *mask,
+                   int32_t *lo, int32_t *hi, int32_t *dstar, double *dz);
+int orc_reduced_frame(const orc_params *prm, const uint8_t *left, const uint8_t *right,
+                      const double T[16], double *d, double *p, uint8_t *sflags, uint8_t *mask,
+                      double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi,
+                      int32_t *dstar, double *dz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
