@@ -1,0 +1,73 @@
+"""ctypes declarations of libsgm.so (the C ABI in include/sgm.h).
+
+Loading fails loudly when the library has not been built: there is no
+fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgm.so")
+
+SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_ESTATE = 0, -1, -2, -3, -4
+FLAG_PRED, FLAG_RESET, FLAG_FULLWIN = 1, 2, 4
+(STAGE_CENSUS_L, STAGE_CENSUS_R, STAGE_LO, STAGE_HI, STAGE_OFFSETS, STAGE_COST, STAGE_SUM, STAGE_DHAT,
+ STAGE_PM, STAGE_FLAGS, STAGE_DSTAR, STAGE_DZ, STAGE_STATUS) = range(13)
+STAGE_PATH0 = 16
+
+# every symbol include/sgm.h declares
+EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
+           "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_state", "sgm_set_state",
+           "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_last_error")
+
+
+class SgmParams(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("max_disp", ctypes.c_int32),
+                ("census_w", ctypes.c_int32), ("census_h", ctypes.c_int32), ("path_mask", ctypes.c_uint32),
+                ("p1", ctypes.c_int32), ("p2", ctypes.c_int32),
+                ("k_sigma", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
+                ("chi2_gate", ctypes.c_double), ("disc_thresh", ctypes.c_double),
+                ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
+                ("baseline", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libsgm.so and declare its functions (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    sig = {
+        "sgm_default_params": [ctypes.POINTER(SgmParams), I32, I32, I32],
+        "sgm_create": [ctypes.POINTER(SgmParams), ctypes.POINTER(P)],
+        "sgm_destroy": [P],
+        "sgm_full_frame": [P, P, P, I32, P],
+        "sgm_reduced_frame": [P, P, P, I32, ctypes.POINTER(ctypes.c_double), P],
+        "sgm_get_disparity": [P, P, I32, P],
+        "sgm_get_variance": [P, P, I32, P],
+        "sgm_get_motion_mask": [P, P, I32, P],
+        "sgm_get_state": [P, P, P, P, P],
+        "sgm_set_state": [P, P, P, P, P],
+        "sgm_match_windows": [P, P, P, I32, P, P, P, P, P],
+        "sgm_get_stage": [P, I32, P, SZ, P],
+        "sgm_cost_cells": [P, ctypes.POINTER(I64), P],
+        "sgm_set_debug": [P, I32],
+        "sgm_last_error": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.sgm_destroy.restype = None
+    lib.sgm_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib

@@ -1,0 +1,515 @@
+// C ABI of the gfx950 library: context management, argument checks and the
+// per-frame launch sequences.  Every entry point is declared, with its
+// contract, in include/sgm.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "sgm_internal.h"
+
+using namespace sgmk;
+
+struct sgm_context {
+    sgm_params prm;
+    Geometry g;
+    DevBuffers b;
+    bool started;
+    bool debug;
+    int device;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(SGM_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+const int8_t kPathDx[8] = {+1, -1, 0, 0, +1, -1, -1, +1};
+const int8_t kPathDy[8] = {0, 0, +1, -1, +1, -1, +1, -1};
+
+int validate(const sgm_params *p)
+{
+    if (!p)
+        return fail(SGM_EINVAL, "params is NULL");
+    if (p->width < 16 || p->height < 16 || (int64_t)p->width * p->height > (1 << 24))
+        return fail(SGM_EINVAL, "image size %dx%d outside [16, 2^24 pixels]", p->width, p->height);
+    if (p->max_disp < 2 || p->max_disp > kMaxDisp)
+        return fail(SGM_EINVAL, "max_disp %d outside [2, %d]", p->max_disp, kMaxDisp);
+    if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1) || p->census_w > 15 ||
+        p->census_h > 15 || p->census_w * p->census_h - 1 > 64)
+        return fail(SGM_EINVAL, "census window %dx%d must be odd, <= 15 and hold <= 64 bits", p->census_w,
+                    p->census_h);
+    int nbits = p->census_w * p->census_h - 1;
+    if (p->p1 < 0 || p->p2 < p->p1)
+        return fail(SGM_EINVAL, "penalties must satisfy 0 <= P1 <= P2 (got %d, %d)", p->p1, p->p2);
+    if (nbits + p->p2 + p->p1 > 255)
+        return fail(SGM_EINVAL, "census bits + P2 + P1 = %d exceeds the 8-bit path loss", nbits + p->p2 + p->p1);
+    if ((p->path_mask & 0xFFu) == 0 || (p->path_mask & ~0xFFu))
+        return fail(SGM_EINVAL, "path_mask 0x%x must select 1..8 of the paths 0..7", p->path_mask);
+    if (!(p->k_sigma > 0) || !(p->q >= 0) || !(p->r > 0) || !(p->chi2_gate > 0) || !(p->disc_thresh >= 0))
+        return fail(SGM_EINVAL, "need k_sigma > 0, q >= 0, r > 0, chi2_gate > 0, disc_thresh >= 0");
+    if (!(p->f > 0) || !(p->baseline > 0) || !isfinite(p->cx) || !isfinite(p->cy))
+        return fail(SGM_EINVAL, "need f > 0, baseline > 0 and a finite principal point");
+    return SGM_OK;
+}
+
+template <class T>
+hipError_t dalloc(T **ptr, size_t count)
+{
+    return hipMalloc((void **)ptr, count * sizeof(T) + 256);
+}
+
+void free_buffers(DevBuffers &b)
+{
+    void *all[] = {b.cen_l, b.cen_r, b.win,    b.off,    b.scan_part, b.cost,  b.lr,   b.sum,  b.d,   b.p,
+                   b.sflags, b.mask, b.dhat,   b.pm,     b.flags,     b.dstar, b.dz,   b.zkey, b.zidx, b.tgt,
+                   b.dprime, b.pprime, b.has, b.rw,     b.pred,      b.rst,   b.dw,   b.pw,   b.dfill, b.pfill,
+                   b.status};
+    for (void *p : all)
+        if (p)
+            (void)hipFree(p);
+    memset(&b, 0, sizeof(b));
+}
+
+hipStream_t as_stream(void *s) { return (hipStream_t)s; }
+
+int check_ctx(sgm_context *ctx)
+{
+    if (!ctx)
+        return fail(SGM_EINVAL, "context is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ctx->device)
+        return fail(SGM_EINVAL, "context was created on device %d but device %d is current", ctx->device, dev);
+    return SGM_OK;
+}
+
+int check_images(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch)
+{
+    if (!l || !r)
+        return fail(SGM_EINVAL, "image pointer is NULL");
+    if (pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "pitch %d < width %d", pitch, ctx->g.W);
+    return SGM_OK;
+}
+
+CorrectConst correct_const(const sgm_params &p)
+{
+    CorrectConst c;
+    c.r = p.r;
+    c.gate = p.chi2_gate;
+    c.k_sigma = p.k_sigma;
+    c.disc = p.disc_thresh;
+    return c;
+}
+
+// census, cost, aggregation, WTA (+ filter update in modes 0 and 1)
+int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, int mode, hipStream_t s)
+{
+    const Geometry &g = ctx->g;
+    DevBuffers &b = ctx->b;
+    hipError_t e = launch_census(g, l, r, pitch, b.cen_l, b.cen_r, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "census launch");
+    e = launch_cost(g, b, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "cost launch");
+    e = launch_aggregate(g, b, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "aggregation launch");
+    e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "wta launch");
+    return SGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sgm_last_error(void) { return g_err; }
+
+int sgm_default_params(sgm_params *out, int32_t width, int32_t height, int32_t max_disp)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    memset(out, 0, sizeof(*out));
+    out->width = width;
+    out->height = height;
+    out->max_disp = max_disp;
+    out->census_w = 9;
+    out->census_h = 7;
+    out->path_mask = 0xFF;
+    out->p1 = 7;
+    out->p2 = 86;
+    out->k_sigma = 3.0;
+    out->q = 0.5;
+    out->r = 1.0;
+    out->chi2_gate = 6.634896601021214;
+    out->disc_thresh = 2.0;
+    out->f = 0.58 * width;
+    out->cx = (width - 1) / 2.0;
+    out->cy = (height - 1) / 2.0;
+    out->baseline = 0.54;
+    return SGM_OK;
+}
+
+int sgm_create(const sgm_params *prm, sgm_context **out)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(prm);
+    if (rc)
+        return rc;
+    sgm_context *ctx = new (std::nothrow) sgm_context();
+    if (!ctx)
+        return fail(SGM_ENOMEM, "host allocation failed");
+    ctx->prm = *prm;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return fail(SGM_EHIP, "no HIP device");
+    }
+    Geometry &g = ctx->g;
+    g.W = prm->width;
+    g.H = prm->height;
+    g.D = prm->max_disp;
+    g.N = g.W * g.H;
+    g.cw = prm->census_w;
+    g.ch = prm->census_h;
+    g.nbits = g.cw * g.ch - 1;
+    g.p1 = prm->p1;
+    g.p2 = prm->p2;
+    g.npaths = 0;
+    for (int k = 0; k < 8; k++)
+        if (prm->path_mask & (1u << k)) {
+            g.rx[g.npaths] = kPathDx[k];
+            g.ry[g.npaths] = kPathDy[k];
+            g.npaths++;
+        }
+    const size_t N = g.N, cells = N * (size_t)g.D;
+    DevBuffers &b = ctx->b;
+    memset(&b, 0, sizeof(b));
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess)
+            e = r;
+    };
+    A(dalloc(&b.cen_l, N));
+    A(dalloc(&b.cen_r, N));
+    A(dalloc(&b.win, N));
+    A(dalloc(&b.off, N + 1));
+    A(dalloc(&b.scan_part, 4200));
+    A(dalloc(&b.cost, cells));
+    A(dalloc(&b.lr, cells * g.npaths));
+    A(dalloc(&b.sum, cells));
+    A(dalloc(&b.d, N));
+    A(dalloc(&b.p, N));
+    A(dalloc(&b.sflags, N));
+    A(dalloc(&b.mask, N));
+    A(dalloc(&b.dhat, N));
+    A(dalloc(&b.pm, N));
+    A(dalloc(&b.flags, N));
+    A(dalloc(&b.dstar, N));
+    A(dalloc(&b.dz, N));
+    A(dalloc(&b.zkey, N));
+    A(dalloc(&b.zidx, N));
+    A(dalloc(&b.tgt, N));
+    A(dalloc(&b.dprime, N));
+    A(dalloc(&b.pprime, N));
+    A(dalloc(&b.has, N));
+    A(dalloc(&b.rw, N));
+    A(dalloc(&b.pred, N));
+    A(dalloc(&b.rst, N));
+    A(dalloc(&b.dw, N));
+    A(dalloc(&b.pw, N));
+    A(dalloc(&b.dfill, N));
+    A(dalloc(&b.pfill, N));
+    A(dalloc(&b.status, 4));
+    if (e != hipSuccess) {
+        free_buffers(b);
+        delete ctx;
+        return fail(SGM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    // z-buffer armed (key 0, no index); state zeroed; all synchronous
+    A(hipMemset(b.zkey, 0, N * sizeof(unsigned long long)));
+    A(hipMemset(b.zidx, 0xFF, N * sizeof(uint32_t)));
+    A(hipMemset(b.d, 0, N * sizeof(double)));
+    A(hipMemset(b.p, 0, N * sizeof(double)));
+    A(hipMemset(b.sflags, 0, N));
+    A(hipMemset(b.mask, 0, N));
+    A(hipMemset(b.flags, 0, N));
+    A(hipMemset(b.dhat, 0, N * sizeof(double)));
+    A(hipMemset(b.pm, 0, N * sizeof(double)));
+    A(hipMemset(b.off, 0, (N + 1) * sizeof(uint32_t)));
+    A(hipMemset(b.status, 0, sizeof(uint32_t)));
+    A(hipDeviceSynchronize());
+    if (e != hipSuccess) {
+        free_buffers(b);
+        delete ctx;
+        return hip_fail(e, "initialisation");
+    }
+    ctx->started = false;
+    ctx->debug = false;
+    *out = ctx;
+    return SGM_OK;
+}
+
+void sgm_destroy(sgm_context *ctx)
+{
+    if (!ctx)
+        return;
+    (void)hipDeviceSynchronize();
+    free_buffers(ctx->b);
+    delete ctx;
+}
+
+int sgm_set_debug(sgm_context *ctx, int32_t on)
+{
+    if (!ctx)
+        return fail(SGM_EINVAL, "context is NULL");
+    ctx->debug = on != 0;
+    return SGM_OK;
+}
+
+int sgm_full_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc || (rc = check_images(ctx, left, right, pitch)))
+        return rc;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "window launch");
+    rc = run_matcher(ctx, left, right, pitch, 0, s);
+    if (rc)
+        return rc;
+    ctx->started = true;
+    return SGM_OK;
+}
+
+int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                      const double T[16], void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc || (rc = check_images(ctx, left, right, pitch)))
+        return rc;
+    if (!T)
+        return fail(SGM_EINVAL, "T_k_km1 is NULL");
+    for (int i = 0; i < 16; i++)
+        if (!isfinite(T[i]))
+            return fail(SGM_EINVAL, "T_k_km1[%d] is not finite", i);
+    if (!ctx->started)
+        return fail(SGM_ESTATE, "reduced frame requested before a full frame or set_state");
+    const sgm_params &p = ctx->prm;
+    WarpConst wc;
+    for (int i = 0; i < 12; i++)
+        wc.T[i] = T[i];
+    wc.f = p.f;
+    wc.cx = p.cx;
+    wc.cy = p.cy;
+    wc.B = p.baseline;
+    wc.fB = p.f * p.baseline;
+    wc.zmin = 1e-9 * wc.fB;
+    wc.q = p.q;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_predict(ctx->g, ctx->b, wc, correct_const(p), s);
+    if (e != hipSuccess)
+        return hip_fail(e, "prediction launch");
+    return run_matcher(ctx, left, right, pitch, 1, s);
+}
+
+int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                      const int32_t *lo, const int32_t *hi, int32_t *dstar, double *dz, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc || (rc = check_images(ctx, left, right, pitch)))
+        return rc;
+    if (!lo || !hi || !dstar || !dz)
+        return fail(SGM_EINVAL, "window or output pointer is NULL");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = launch_given_windows(ctx->g, ctx->b, lo, hi, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "window launch");
+    rc = run_matcher(ctx, left, right, pitch, 2, s);
+    if (rc)
+        return rc;
+    const size_t N = ctx->g.N;
+    e = hipMemcpyAsync(dstar, ctx->b.dstar, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(dz, ctx->b.dz, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "output copy");
+    return SGM_OK;
+}
+
+int sgm_get_disparity(sgm_context *ctx, float *out, int32_t out_pitch, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!out || out_pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "bad output pointer or pitch");
+    hipError_t e = launch_state_to_f32(ctx->g, ctx->b.d, out, out_pitch, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "conversion launch");
+}
+
+int sgm_get_variance(sgm_context *ctx, float *out, int32_t out_pitch, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!out || out_pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "bad output pointer or pitch");
+    hipError_t e = launch_state_to_f32(ctx->g, ctx->b.p, out, out_pitch, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "conversion launch");
+}
+
+int sgm_get_motion_mask(sgm_context *ctx, uint8_t *out, int32_t out_pitch, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!out || out_pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "bad output pointer or pitch");
+    hipError_t e = launch_copy_u8(ctx->g, ctx->b.mask, out, out_pitch, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "copy launch");
+}
+
+int sgm_get_state(sgm_context *ctx, double *d, double *p, uint8_t *sflags, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!d || !p || !sflags)
+        return fail(SGM_EINVAL, "state pointer is NULL");
+    const size_t N = ctx->g.N;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(d, ctx->b.d, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(p, ctx->b.p, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sflags, ctx->b.sflags, N, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "state copy");
+}
+
+int sgm_set_state(sgm_context *ctx, const double *d, const double *p, const uint8_t *sflags, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!d || !p || !sflags)
+        return fail(SGM_EINVAL, "state pointer is NULL");
+    const size_t N = ctx->g.N;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(ctx->b.d, d, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->b.p, p, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->b.sflags, sflags, N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "state copy");
+    ctx->started = true;
+    return SGM_OK;
+}
+
+int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!cells)
+        return fail(SGM_EINVAL, "cells is NULL");
+    uint32_t m = 0;
+    hipStream_t s = as_stream(stream);
+    hipError_t e = hipMemcpyAsync(&m, ctx->b.off + ctx->g.N, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "cell count read-back");
+    *cells = m;
+    return SGM_OK;
+}
+
+int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    const Geometry &g = ctx->g;
+    const DevBuffers &b = ctx->b;
+    const size_t N = g.N;
+    hipStream_t s = as_stream(stream);
+    const void *src = nullptr;
+    size_t need = 0;
+    size_t M = 0;
+    if (stage == SGM_STAGE_COST || stage == SGM_STAGE_SUM || stage >= SGM_STAGE_PATH0) {
+        int64_t m = 0;
+        rc = sgm_cost_cells(ctx, &m, stream);
+        if (rc)
+            return rc;
+        M = (size_t)m;
+    }
+    switch (stage) {
+    case SGM_STAGE_CENSUS_L: src = b.cen_l; need = N * 8; break;
+    case SGM_STAGE_CENSUS_R: src = b.cen_r; need = N * 8; break;
+    case SGM_STAGE_OFFSETS: src = b.off; need = (N + 1) * 4; break;
+    case SGM_STAGE_COST: src = b.cost; need = M; break;
+    case SGM_STAGE_SUM:
+        if (!ctx->debug)
+            return fail(SGM_EINVAL, "SGM_STAGE_SUM needs sgm_set_debug(ctx, 1) before the frame");
+        src = b.sum; need = M * 2; break;
+    case SGM_STAGE_DHAT: src = b.dhat; need = N * 8; break;
+    case SGM_STAGE_PM: src = b.pm; need = N * 8; break;
+    case SGM_STAGE_FLAGS: src = b.flags; need = N; break;
+    case SGM_STAGE_DSTAR: src = b.dstar; need = N * 4; break;
+    case SGM_STAGE_DZ: src = b.dz; need = N * 8; break;
+    case SGM_STAGE_STATUS: src = b.status; need = 4; break;
+    case SGM_STAGE_LO:
+    case SGM_STAGE_HI: {
+        if (bytes != N * 4)
+            return fail(SGM_EINVAL, "stage %d needs %zu bytes, got %zu", stage, N * 4, bytes);
+        hipError_t e = launch_windows_to_lohi(g, b, (int32_t *)out, stage == SGM_STAGE_HI, s);
+        return e == hipSuccess ? SGM_OK : hip_fail(e, "window conversion");
+    }
+    default:
+        if (stage >= SGM_STAGE_PATH0 && stage < SGM_STAGE_PATH0 + 8) {
+            int k = stage - SGM_STAGE_PATH0, idx = -1, n = 0;
+            for (int j = 0; j < 8; j++)
+                if (ctx->prm.path_mask & (1u << j)) {
+                    if (j == k)
+                        idx = n;
+                    n++;
+                }
+            if (idx < 0)
+                return fail(SGM_EINVAL, "path %d is not enabled", k);
+            src = b.lr + (size_t)idx * N * g.D;
+            need = M;
+            break;
+        }
+        return fail(SGM_EINVAL, "unknown stage %d", stage);
+    }
+    if (bytes != need)
+        return fail(SGM_EINVAL, "stage %d needs %zu bytes, got %zu", stage, need, bytes);
+    hipError_t e = hipMemcpyAsync(out, src, need, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "stage copy");
+}
+
+}  // extern "C"

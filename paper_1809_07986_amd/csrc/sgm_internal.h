@@ -1,0 +1,77 @@
+// Internal declarations shared by the kernels and the C ABI of the gfx950
+// library (reduced-space SGM + per-pixel Kalman filter).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sgm.h"
+
+namespace sgmk {
+
+constexpr int kMaxDisp = 256;          // windows are packed as (lo, width-1) bytes
+constexpr int kMaxPaths = 8;
+
+// Device-side layout of one context.  Per-pixel arrays have N = W*H
+// entries in raster order; cost-volume arrays have N*D entries (the worst
+// case: every window full range), of which the first M = off[N] are used.
+struct DevBuffers {
+    uint64_t *cen_l, *cen_r;   // census strings
+    uint16_t *win;             // window: lo | (width-1) << 8
+    uint32_t *off;             // ragged offsets, N+1
+    uint32_t *scan_part;       // scan partial sums
+    uint8_t *cost;             // Hamming cost per cell
+    uint8_t *lr;               // L_r per enabled path, stride N*D
+    uint16_t *sum;             // S per cell (debug only)
+    double *d, *p;             // filter state
+    uint8_t *sflags, *mask;    // RESET for the next frame, moving mask
+    double *dhat, *pm;         // prediction
+    uint8_t *flags;            // SGM_FLAG_* of the frame
+    int32_t *dstar;            // integer winner
+    double *dz;                // sub-pixel measurement
+    // splatting scratch
+    unsigned long long *zkey;  // max d' bits per target
+    uint32_t *zidx;            // min source index among the max-d' sources
+    int32_t *tgt;              // target per source (-1 dropped)
+    double *dprime, *pprime;   // splatted disparity / variance per source
+    uint8_t *has, *rw, *pred, *rst;
+    double *dw, *pw, *dfill, *pfill;
+    uint32_t *status;
+};
+
+struct Geometry {
+    int W, H, D, N;
+    int cw, ch, nbits;
+    int p1, p2;
+    int npaths;
+    int8_t rx[kMaxPaths], ry[kMaxPaths];
+};
+
+struct WarpConst {
+    double T[12];          // rows of [R | t]
+    double f, cx, cy, B, fB, zmin, q;
+};
+
+struct CorrectConst {
+    double r, gate, k_sigma, disc;
+};
+
+// kernel launchers (all asynchronous on `s`); return hipError_t of the launch
+hipError_t launch_census(const Geometry &g, const uint8_t *left, const uint8_t *right, int pitch,
+                         uint64_t *cl, uint64_t *cr, hipStream_t s);
+hipError_t launch_full_windows(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_given_windows(const Geometry &g, DevBuffers &b, const int32_t *lo, const int32_t *hi,
+                                hipStream_t s);
+hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const CorrectConst &cc,
+                          hipStream_t s);
+hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, hipStream_t s);
+// mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only
+hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
+                              bool debug_sum, hipStream_t s);
+hipError_t launch_windows_to_lohi(const Geometry &g, const DevBuffers &b, int32_t *out, int which,
+                                  hipStream_t s);
+hipError_t launch_state_to_f32(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);
+hipError_t launch_copy_u8(const Geometry &g, const uint8_t *src, uint8_t *dst, int pitch, hipStream_t s);
+
+}  // namespace sgmk

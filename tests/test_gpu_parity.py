@@ -1,0 +1,267 @@
+"""GPU library vs the CPU oracle, element by element, through the C ABI.
+
+Tolerances: census, costs, path losses, sums, windows, flags, masks and the
+integer winner are compared bit for bit.  Floating-point state is compared
+against the documented bound (1e-4 px for disparities, 1e-4 relative for
+variances); both sides evaluate the same double-precision operations in the
+same order without FMA contraction, so the observed difference is zero.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import stereo_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1809_07986_amd as sgmk  # noqa: E402
+from paper_1809_07986_amd import _native as NAT  # noqa: E402
+
+D_TOL = 1e-4
+P_TOL = 1e-4
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _params(seq, **kw):
+    return dict(f=seq.cam.f, baseline=seq.cam.baseline, **kw)
+
+
+def _oracle_params(seq, **kw):
+    return O.Params(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline, **kw)
+
+
+def _ragged(vol, lo, hi):
+    D = vol.shape[-1]
+    d = np.arange(D)
+    m = (d[None, None, :] >= lo[:, :, None]) & (d[None, None, :] <= hi[:, :, None])
+    return vol[..., m] if vol.ndim == 4 else vol[m]
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _check_match(g, seq_l, seq_r, prm, lo, hi, label, paths=True):
+    dstar, dz, C, S = O.match(prm, seq_l, seq_r, lo, hi, want_cs=True)
+    g.set_debug(True)
+    gd, gz = g.match_windows(seq_l, seq_r, lo, hi)
+    torch.cuda.synchronize()
+    assert int(_np(g.stage(NAT.STAGE_STATUS))[0]) == 0, label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_LO)), lo), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_HI)), hi), label
+    cl = O.census(seq_l, prm.census_w, prm.census_h)
+    cr = O.census(seq_r, prm.census_w, prm.census_h)
+    assert np.array_equal(_np(g.stage(NAT.STAGE_CENSUS_L)).view(np.uint64), cl), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_CENSUS_R)).view(np.uint64), cr), label
+    cells = int(((hi - lo) + 1).sum())
+    assert g.cost_cells() == cells, label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_COST)).astype(np.int32), _ragged(C, lo, hi)), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_SUM)).view(np.uint16).astype(np.int32), _ragged(S, lo, hi)), label
+    if paths:
+        C2 = np.where(C >= 0, C, 0)
+        S2, Lr = O.aggregate(C2, lo, hi, prm.p1, prm.p2, prm.path_mask, want_lr=True)
+        for k in range(8):
+            if prm.path_mask >> k & 1:
+                got = _np(g.stage(NAT.STAGE_PATH0 + k)).astype(np.int32)
+                assert np.array_equal(got, _ragged(Lr[k], lo, hi)), (label, "path", k)
+    assert np.array_equal(_np(gd), dstar), label
+    gz = _np(gz)
+    assert np.max(np.abs(gz - dz)) <= D_TOL, label
+    return np.max(np.abs(gz - dz))
+
+
+def test_library_loads_on_gpu():
+    lib = NAT.load()
+    for name in NAT.EXPORTS:
+        assert hasattr(lib, name)
+
+
+def test_full_windows_tiny_frame0():
+    seq = synth.make_sequence("tiny")
+    _say("case: tiny frame 0, full windows")
+    g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, **_params(seq))
+    prm = _oracle_params(seq)
+    H, W = seq.cam.height, seq.cam.width
+    lo = np.zeros((H, W), np.int32)
+    hi = np.full((H, W), seq.max_disp - 1, np.int32)
+    diff = _check_match(g, seq.left[0], seq.right[0], prm, lo, hi, "tiny-full")
+    _say(f"max |dz diff| = {diff}")
+
+
+@pytest.mark.parametrize("seed,full_frac,maxw", [(0, 0.1, 12), (1, 0.0, 4), (2, 0.3, 20), (3, 0.02, 1)])
+def test_ragged_windows_tiny(seed, full_frac, maxw):
+    seq = synth.make_sequence("tiny")
+    _say(f"case: tiny ragged windows seed={seed}")
+    g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, **_params(seq))
+    prm = _oracle_params(seq)
+    rng = np.random.default_rng(seed)
+    lo, hi = synth.random_windows(rng, seq.cam.height, seq.cam.width, seq.max_disp, max_width=maxw,
+                                  full_frac=full_frac, smooth=seed % 2 == 0)
+    _check_match(g, seq.left[1], seq.right[1], prm, lo, hi, f"ragged-{seed}")
+
+
+@pytest.mark.parametrize("W,H,D,mask,cw,ch", [
+    (16, 16, 2, 0xFF, 9, 7),        # smallest image, two disparities
+    (37, 19, 256, 0xFF, 9, 7),      # widest range, ragged tiles
+    (70, 33, 48, 0x0F, 9, 7),       # nondiagonal paths
+    (70, 33, 48, 0xF0, 9, 7),       # diagonal paths
+    (53, 29, 40, 0x40, 5, 5),       # single path, 5x5 census (generic kernel)
+    (45, 21, 30, 0xFF, 7, 9),       # tall census window
+])
+def test_shapes_paths_and_census(W, H, D, mask, cw, ch):
+    _say(f"case: shape {W}x{H}x{D} mask={mask:#x} census {cw}x{ch}")
+    rng = np.random.default_rng(W * 1000 + H)
+    left = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    shift = min(3, D - 1)
+    right = np.roll(left, -shift, axis=1)
+    g = sgmk.ReducedSGM(W, H, D, path_mask=mask, census_w=cw, census_h=ch, f=100.0)
+    prm = O.Params(W, H, D, path_mask=mask, census_w=cw, census_h=ch, f=100.0)
+    lo, hi = synth.random_windows(rng, H, W, D, max_width=9, full_frac=0.15)
+    _check_match(g, left, right, prm, lo, hi, f"shape-{W}x{H}x{D}")
+    lo = np.zeros((H, W), np.int32)
+    hi = np.full((H, W), D - 1, np.int32)
+    _check_match(g, left, right, prm, lo, hi, f"shape-full-{W}x{H}x{D}")
+
+
+def test_pitched_images():
+    seq = synth.make_sequence("tiny")
+    H, W = seq.cam.height, seq.cam.width
+    _say("case: pitched input rows")
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+    pad = 64
+    Lp = torch.zeros((H, W + pad), dtype=torch.uint8, device="cuda")
+    Rp = torch.zeros((H, W + pad), dtype=torch.uint8, device="cuda")
+    Lp[:, :W] = torch.from_numpy(seq.left[0]).cuda()
+    Rp[:, :W] = torch.from_numpy(seq.right[0]).cuda()
+    lib = NAT.load()
+    stream = torch.cuda.current_stream().cuda_stream
+    sgmk._check(lib.sgm_full_frame(g._h, Lp.data_ptr(), Rp.data_ptr(), W + pad, stream))
+    d1 = g.disparity()
+    g2 = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+    g2.full_frame(seq.left[0], seq.right[0])
+    torch.cuda.synchronize()
+    assert torch.equal(d1, g2.disparity())
+
+
+def _compare_state(g, F, label, frame_has_pred):
+    d, p, sf = (_np(t) for t in g.get_state())
+    assert np.max(np.abs(d - F.d)) <= D_TOL, label
+    assert np.max(np.abs(p - F.p) / np.maximum(F.p, 1e-12)) <= P_TOL, label
+    assert np.array_equal(sf, F.sflags), label
+    assert np.array_equal(_np(g.motion_mask()), F.mask), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_LO)), F.lo), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_HI)), F.hi), label
+    assert np.array_equal(_np(g.stage(NAT.STAGE_DSTAR)), F.dstar), label
+    assert np.max(np.abs(_np(g.stage(NAT.STAGE_DZ)) - F.dz)) <= D_TOL, label
+    if frame_has_pred:
+        assert np.array_equal(_np(g.stage(NAT.STAGE_FLAGS)), F.flags), label
+        assert np.max(np.abs(_np(g.stage(NAT.STAGE_DHAT)) - F.dhat)) <= D_TOL, label
+        assert np.max(np.abs(_np(g.stage(NAT.STAGE_PM)) - F.pm)) <= P_TOL, label
+    exact = (np.array_equal(d, F.d) and np.array_equal(p, F.p))
+    _say(f"{label}: state bit-identical={exact}")
+
+
+def _run_sequence(seq, frames, label):
+    H, W = seq.cam.height, seq.cam.width
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+    F = O.OracleFilter(_oracle_params(seq))
+    for k in range(frames):
+        _say(f"case: {label} frame {k}")
+        if k == 0:
+            g.full_frame(seq.left[0], seq.right[0])
+            F.full_frame(seq.left[0], seq.right[0])
+        else:
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+            F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        torch.cuda.synchronize()
+        _compare_state(g, F, f"{label} frame {k}", k > 0)
+        assert g.cost_cells() == int((F.hi - F.lo + 1).sum())
+    return g, F
+
+
+def test_free_running_tiny_sequence():
+    seq = synth.make_sequence("tiny")
+    _run_sequence(seq, seq.frames, "tiny")
+
+
+def test_injected_state_prediction_stage():
+    # the oracle's state is injected, so prediction parity does not depend on
+    # earlier frames; includes RESET flags and a lateral + yaw motion
+    seq = synth.make_sequence("tiny")
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    rng = np.random.default_rng(5)
+    d, p, sf = synth.random_state(rng, H, W, D)
+    sf = np.where(rng.random((H, W)) < 0.05, O.RESET, 0).astype(np.uint8)
+    c, s_ = np.cos(0.02), np.sin(0.02)
+    T = np.array([[c, 0, s_, 0.05], [0, 1, 0, 0.01], [-s_, 0, c, -0.4], [0, 0, 0, 1.0]])
+    g = sgmk.ReducedSGM(W, H, D, **_params(seq))
+    F = O.OracleFilter(_oracle_params(seq))
+    g.set_state(d, p, sf)
+    F.set_state(d, p, sf)
+    _say("case: injected state + reduced frame")
+    g.reduced_frame(seq.left[1], seq.right[1], T)
+    F.reduced_frame(seq.left[1], seq.right[1], T)
+    torch.cuda.synchronize()
+    _compare_state(g, F, "injected", True)
+
+
+def test_reduced_before_full_is_an_error():
+    g = sgmk.ReducedSGM(32, 16, 16)
+    img = np.zeros((16, 32), np.uint8)
+    with pytest.raises(sgmk.SgmError) as e:
+        g.reduced_frame(img, img, np.eye(4))
+    assert e.value.code == NAT.SGM_ESTATE
+
+
+def test_invalid_params_rejected():
+    for kw in (dict(p1=90, p2=80), dict(census_w=11, census_h=7), dict(path_mask=0),
+               dict(max_disp=300), dict(r=0.0)):
+        md = kw.pop("max_disp", 32)
+        with pytest.raises(sgmk.SgmError) as e:
+            sgmk.ReducedSGM(32, 16, md, **kw)
+        assert e.value.code == NAT.SGM_EINVAL
+
+
+def test_invalid_windows_are_clamped_and_counted():
+    g = sgmk.ReducedSGM(32, 16, 16)
+    img = np.random.default_rng(0).integers(0, 256, (16, 32)).astype(np.uint8)
+    lo = np.zeros((16, 32), np.int32)
+    hi = np.full((16, 32), 15, np.int32)
+    lo[0, 0] = -3
+    hi[1, 1] = 40
+    g.match_windows(img, img, lo, hi)
+    torch.cuda.synchronize()
+    assert int(_np(g.stage(NAT.STAGE_STATUS))[0]) == 2
+
+
+def test_deterministic_repeat():
+    seq = synth.make_sequence("tiny")
+    H, W = seq.cam.height, seq.cam.width
+    outs = []
+    for _ in range(2):
+        g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+        g.full_frame(seq.left[0], seq.right[0])
+        for k in range(1, seq.frames):
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        torch.cuda.synchronize()
+        outs.append([_np(t) for t in g.get_state()] + [_np(g.motion_mask())])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
+def test_driving_full_size_sequence():
+    # the benchmark workload at full size (1242x375, D=128): census, the full
+    # frame and two reduced frames against the oracle, every pixel
+    seq = synth.make_sequence("driving", frames=3)
+    _run_sequence(seq, 3, "driving")
