@@ -1,0 +1,266 @@
+#!/usr/bin/env python3
+"""Throughput of reduced-space SGM + per-pixel Kalman filter on one MI355X.
+
+Workload: the synthetic driving sequence, 1242x375, disparities 0..127,
+census 9x7, 8 paths, P1=7, P2=86 (20 rendered frames).  Frame 0 is a
+full-range frame; every timed step is one steady-state frame (prediction,
+reduced-window matching, Kalman correction, innovation test) on left/right
+images already resident in HBM.  The frames are visited 1..19 and then
+back (19..1 with the inverse ego-motion), which keeps every step a valid
+stereo sequence step.  Full-range SGM (every window [0, 127]) is timed on the
+same frames for comparison.
+
+Prints one JSON line (rank 0): frames/s of the reduced path as `value`, plus
+cost-cells/s, the full-range figures, a roofline object for the dominant
+kernel (HIP events on the library's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "frames/s and cost-cells/s, reduced vs full SGM at 1242×375×128, 1 GPU"
+# algorithmic bytes of the aggregation schedule:
+# per cell and path: read the cost byte, write the path-loss byte;
+# per pixel and path: read the ragged offset (4 B) and window (2 B)
+AGG_BYTES_PER_CELL_PATH = 2
+AGG_BYTES_PER_PIXEL_PATH = 6
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aggregate_driving.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_1809_07986_amd", "csrc", "sgm_kernels.hip")
+
+
+def frame_schedule(n_frames: int, steps: int):
+    """(from, to) frame pairs of `steps` reduced steps: 0->1->..->K-1, then back."""
+    out = []
+    k, direction = 0, +1
+    while len(out) < steps:
+        if k + direction < 0 or k + direction > n_frames - 1:
+            direction = -direction
+        k_next = k + direction
+        out.append((k, k_next))
+        k = k_next
+    return out
+
+
+def T_between(seq, k_from: int, k_to: int) -> np.ndarray:
+    if k_to == k_from + 1:
+        return seq.T[k_to]
+    assert k_to == k_from - 1
+    return np.linalg.inv(seq.T[k_from])
+
+
+def source_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic():
+    """Per-launch HBM bytes of the aggregation kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha") != source_sha():
+        return None, kv.get("source_sha")
+    try:
+        return float(kv["bytes_per_launch"]), kv.get("source_sha")
+    except (KeyError, ValueError):
+        return None, None
+
+
+def cpu_baseline(seq, frames: int):
+    import oracle as O
+    prm = O.Params(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    F = O.OracleFilter(prm)
+    F.full_frame(seq.left[0], seq.right[0])   # untimed set-up
+    t0 = time.perf_counter()
+    cells = 0
+    for k in range(1, frames + 1):
+        F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        cells += int((F.hi - F.lo + 1).sum())
+    dt = time.perf_counter() - t0
+    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"driving 1242x375x128, reduced frames 1-{frames} after an untimed full frame 0 "
+                      f"(single-threaded C oracle, {cells / frames / 1e6:.2f} M cells/frame, "
+                      f"{cells / dt / 1e6:.1f} M cells/s)",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=40)
+    ap.add_argument("--full-steps", type=int, default=100)
+    ap.add_argument("--cpu-frames", type=int, default=4)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent streams would shard one per GPU with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1809_07986_amd as sgmk
+    from stereo_synth import make_sequence
+
+    seq = make_sequence("driving")
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    Ls = torch.from_numpy(seq.left).to(dev)
+    Rs = torch.from_numpy(seq.right).to(dev)
+    params = dict(f=seq.cam.f, baseline=seq.cam.baseline)
+    sched = frame_schedule(seq.frames, args.warmup + args.steps)
+    Ts = [sgmk.as_matrix(T_between(seq, a, b)) for a, b in sched]
+
+    if args.copy_mib:
+        n = args.copy_mib << 20
+        src = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}), file=sys.stderr)
+
+    # ---- untimed accounting pass: cells per step and accuracy ------------
+    g = sgmk.ReducedSGM(W, H, D, **params)
+    g.full_frame(Ls[0], Rs[0])
+    cells = []
+    bad_d, bad_z, nval = 0, 0, 0
+    for i, ((a, b), T) in enumerate(zip(sched, Ts)):
+        g.reduced_frame(Ls[b], Rs[b], T)
+        cells.append(g.cost_cells())
+        if i < seq.frames - 1:      # first sweep 1..19: accuracy against the generator's truth
+            v = torch.from_numpy(seq.valid[b]).to(dev)
+            gt = torch.from_numpy(seq.disp_gt[b].astype(np.float32)).to(dev)
+            d = g.disparity()
+            dz = g.stage(sgmk.N.STAGE_DZ).float()
+            bad_d += int(((d - gt).abs() > 3)[v].sum())
+            bad_z += int(((dz - gt).abs() > 3)[v].sum())
+            nval += int(v.sum())
+    timed_cells = sum(cells[args.warmup:])
+    g.close()
+
+    # ---- timed reduced pass (headline) -----------------------------------
+    g = sgmk.ReducedSGM(W, H, D, **params)
+    g.full_frame(Ls[0], Rs[0])
+    for i in range(args.warmup):
+        a, b = sched[i]
+        g.reduced_frame(Ls[b], Rs[b], Ts[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        a, b = sched[i]
+        g.reduced_frame(Ls[b], Rs[b], Ts[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fps = args.steps / dt
+
+    # ---- same steps again with per-stage HIP events (roofline) ------------
+    g.close()
+    g = sgmk.ReducedSGM(W, H, D, **params)
+    g.full_frame(Ls[0], Rs[0])
+    for i in range(args.warmup):
+        a, b = sched[i]
+        g.reduced_frame(Ls[b], Rs[b], Ts[i])
+    torch.cuda.synchronize()
+    g.set_profiling(True)
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        a, b = sched[i]
+        g.reduced_frame(Ls[b], Rs[b], Ts[i])
+    torch.cuda.synchronize()
+    dt_prof = time.perf_counter() - t0
+    stage_ms, nprof = g.read_profile()
+    g.close()
+    stage_avg = {k: v / max(nprof, 1) for k, v in stage_ms.items()}
+
+    # ---- full-range SGM on the same frames --------------------------------
+    gf = sgmk.ReducedSGM(W, H, D, **params)
+    for i in range(5):
+        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.full_steps):
+        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+    torch.cuda.synchronize()
+    dtf = time.perf_counter() - t0
+    full_fps = args.full_steps / dtf
+    gf.set_profiling(True)
+    for i in range(args.full_steps):
+        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+    full_stage_ms, nf = gf.read_profile()
+    full_bad = 0
+    for k in range(1, seq.frames):
+        gf.full_frame(Ls[k], Rs[k])
+        v = torch.from_numpy(seq.valid[k]).to(dev)
+        gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).to(dev)
+        full_bad += int(((gf.disparity() - gt).abs() > 3)[v].sum())
+    gf.close()
+
+    # ---- roofline of the dominant kernel ---------------------------------
+    dom = max(stage_avg, key=stage_avg.get)
+    npaths = 8
+    mean_cells = timed_cells / args.steps
+    agg_bytes = npaths * (AGG_BYTES_PER_CELL_PATH * mean_cells + AGG_BYTES_PER_PIXEL_PATH * H * W)
+    agg_ms = stage_avg["aggregate"]
+    achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
+    traffic, traffic_sha = read_traffic()
+    roofline = {"bound": "hbm", "kernel": "k_aggregate (8-path Eq. 1 aggregation)",
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "algorithmic_bytes_per_launch": int(agg_bytes), "avg_launch_ms": round(agg_ms, 5),
+                "dominant_stage": dom}
+
+    out = {
+        "metric": METRIC,
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "driving sequence 1242x375, disparities 0-127, census 9x7, 8 paths, P1=7, "
+                               "P2=86, reduced-space Kalman SGM steady-state frames (frames 1..19..1)",
+                   "state_dtype": "f64", "cost_dtype": "u8", "path_loss_dtype": "u8", "sum_dtype": "u16"},
+        "cost_cells_per_s": round(timed_cells / dt, 1),
+        "mean_cells_per_frame": round(mean_cells, 1),
+        "full_cells_per_frame": H * W * D,
+        "full_range": {"frames_per_s": round(full_fps, 2), "ms_per_frame": round(dtf / args.full_steps * 1e3, 4),
+                       "cost_cells_per_s": round(full_fps * H * W * D, 1),
+                       "stage_ms": {k: round(v / max(nf, 1), 5) for k, v in full_stage_ms.items()}},
+        "speedup_vs_full": round(fps / full_fps, 3),
+        "stage_ms": {k: round(v, 5) for k, v in stage_avg.items()},
+        "ms_per_step_with_events": round(dt_prof / args.steps * 1e3, 4),
+        "bad_px_gt3": {"reduced_d": round(bad_d / max(nval, 1), 6), "reduced_dz": round(bad_z / max(nval, 1), 6),
+                       "full_range": round(full_bad / max(nval, 1), 6), "frames": "1-19"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        cb = cpu_baseline(seq, args.cpu_frames)
+        out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

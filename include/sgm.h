@@ -51,7 +51,7 @@ extern "C" {
 typedef struct sgm_context sgm_context;
 
 typedef struct {
-    int32_t width, height;      /* image size, 16 <= width, height; width*height <= 2^24 */
+    int32_t width, height;      /* 16 <= width <= 4096, 16 <= height, width*height <= 2^24 */
     int32_t max_disp;           /* disparities 0..max_disp-1, 2 <= max_disp <= 256 */
     int32_t census_w, census_h; /* odd census window, census_w*census_h-1 <= 64 bits */
     uint32_t path_mask;         /* bit k enables path k: 0 (+1,0) 1 (-1,0) 2 (0,+1) 3 (0,-1)
@@ -121,7 +121,8 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
  *   SGM_STAGE_CENSUS_L / _R  uint64 per pixel
  *   SGM_STAGE_LO / _HI       int32 per pixel (window of the last frame)
  *   SGM_STAGE_OFFSETS        uint32, width*height+1 entries
- *   SGM_STAGE_COST           uint8 per cell (Hamming cost)
+ *   SGM_STAGE_COST           uint8 per cell (Hamming cost; recorded only while
+ *                            sgm_set_debug(ctx, 1) is on)
  *   SGM_STAGE_SUM            uint16 per cell (S = sum of L_r; recorded only
  *                            while sgm_set_debug(ctx, 1) is on)
  *   SGM_STAGE_PATH0 + k      uint8 per cell (L_r of path k, enabled paths)
@@ -139,6 +140,18 @@ enum {
 int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream);
 int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
 int sgm_set_debug(sgm_context *ctx, int32_t on);
+
+/* Per-stage GPU time, for benchmarks.  While profiling is on, every frame
+ * records a HIP event before and after each stage's launches on the frame's
+ * own stream (events come from a pool made by sgm_set_profiling, so the
+ * frame path still allocates nothing).  sgm_set_profiling(ctx, 1) starts a
+ * new accumulation, 0 stops it.  sgm_read_profile synchronises `stream`,
+ * then writes the accumulated milliseconds of each stage (SGM_PROF_COUNT
+ * doubles, in the order of the enum) and the number of frames measured. */
+enum { SGM_PROF_CENSUS = 0, SGM_PROF_PREDICT, SGM_PROF_COST, SGM_PROF_AGGREGATE, SGM_PROF_WTA,
+       SGM_PROF_COUNT };
+int sgm_set_profiling(sgm_context *ctx, int32_t on);
+int sgm_read_profile(sgm_context *ctx, double *ms, int64_t *frames, void *stream);
 
 /* Thread-local message describing the last nonzero return on this thread. */
 const char *sgm_last_error(void);

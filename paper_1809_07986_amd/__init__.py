@@ -67,6 +67,11 @@ def default_params(width: int, height: int, max_disp: int, **over) -> N.SgmParam
     return p
 
 
+def as_matrix(T) -> ctypes.Array:
+    """4x4 row-major ego-motion as the double[16] the C ABI takes."""
+    return (ctypes.c_double * 16)(*np.asarray(T, dtype=np.float64).reshape(16).tolist())
+
+
 class ReducedSGM:
     """One stereo stream: owns a library context on the current device."""
 
@@ -99,7 +104,7 @@ class ReducedSGM:
 
     def reduced_frame(self, left, right, T):
         l, r = _dev_image(left, self.device), _dev_image(right, self.device)
-        t = (ctypes.c_double * 16)(*np.asarray(T, dtype=np.float64).reshape(16).tolist())
+        t = T if isinstance(T, ctypes.Array) else as_matrix(T)
         _check(_lib().sgm_reduced_frame(self._h, _ptr(l), _ptr(r), l.shape[1], t, _stream()))
         self._keep = (l, r)
 
@@ -146,6 +151,16 @@ class ReducedSGM:
 
     def set_debug(self, on: bool = True):
         _check(_lib().sgm_set_debug(self._h, 1 if on else 0))
+
+    def set_profiling(self, on: bool = True):
+        _check(_lib().sgm_set_profiling(self._h, 1 if on else 0))
+
+    def read_profile(self):
+        """{stage: accumulated ms}, frames measured (synchronises the stream)."""
+        ms = (ctypes.c_double * len(N.PROF_STAGES))()
+        n = ctypes.c_int64()
+        _check(_lib().sgm_read_profile(self._h, ms, ctypes.byref(n), _stream()))
+        return dict(zip(N.PROF_STAGES, list(ms))), n.value
 
     def cost_cells(self) -> int:
         m = ctypes.c_int64()

@@ -20,7 +20,9 @@ STAGE_PATH0 = 16
 # every symbol include/sgm.h declares
 EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
            "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_state", "sgm_set_state",
-           "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_last_error")
+           "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
+           "sgm_read_profile", "sgm_last_error")
+PROF_STAGES = ("census", "predict", "cost", "aggregate", "wta")
 
 
 class SgmParams(ctypes.Structure):
@@ -61,6 +63,8 @@ def load(path: str = LIB_PATH):
         "sgm_get_stage": [P, I32, P, SZ, P],
         "sgm_cost_cells": [P, ctypes.POINTER(I64), P],
         "sgm_set_debug": [P, I32],
+        "sgm_set_profiling": [P, I32],
+        "sgm_read_profile": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), P],
         "sgm_last_error": [],
     }
     for name, args in sig.items():

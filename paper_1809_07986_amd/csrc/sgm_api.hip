@@ -12,6 +12,18 @@
 
 using namespace sgmk;
 
+// event pool for sgm_set_profiling: kProfFrames frames x stages x {start, end}
+constexpr int kProfFrames = 256;
+
+struct Profiler {
+    bool on = false;
+    hipEvent_t ev[kProfFrames][SGM_PROF_COUNT][2];
+    bool created = false;
+    int pending = 0;                 // frames recorded but not yet read
+    double ms[SGM_PROF_COUNT];
+    int64_t frames = 0;
+};
+
 struct sgm_context {
     sgm_params prm;
     Geometry g;
@@ -19,6 +31,9 @@ struct sgm_context {
     bool started;
     bool debug;
     int device;
+    Profiler prof;
+    hipStream_t side;           // horizontal aggregation runs here, forked from the caller's stream
+    hipEvent_t fork, join;
 };
 
 namespace {
@@ -47,8 +62,9 @@ int validate(const sgm_params *p)
 {
     if (!p)
         return fail(SGM_EINVAL, "params is NULL");
-    if (p->width < 16 || p->height < 16 || (int64_t)p->width * p->height > (1 << 24))
-        return fail(SGM_EINVAL, "image size %dx%d outside [16, 2^24 pixels]", p->width, p->height);
+    if (p->width < 16 || p->height < 16 || p->width > 4096 || (int64_t)p->width * p->height > (1 << 24))
+        return fail(SGM_EINVAL, "image size %dx%d outside 16..4096 wide, >= 16 tall, <= 2^24 pixels", p->width,
+                    p->height);
     if (p->max_disp < 2 || p->max_disp > kMaxDisp)
         return fail(SGM_EINVAL, "max_disp %d outside [2, %d]", p->max_disp, kMaxDisp);
     if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1) || p->census_w > 15 ||
@@ -118,21 +134,81 @@ CorrectConst correct_const(const sgm_params &p)
     return c;
 }
 
+// fold the recorded frames into the totals (waits for their end events)
+hipError_t prof_flush(Profiler &pf)
+{
+    for (int f = 0; f < pf.pending; f++) {
+        for (int st = 0; st < SGM_PROF_COUNT; st++) {
+            hipError_t e = hipEventSynchronize(pf.ev[f][st][1]);
+            if (e != hipSuccess)
+                return e;
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, pf.ev[f][st][0], pf.ev[f][st][1]) == hipSuccess)
+                pf.ms[st] += t;
+        }
+        pf.frames++;
+    }
+    pf.pending = 0;
+    return hipSuccess;
+}
+
+// mark the start / end of a stage of the current frame (no-op unless on)
+struct StageMark {
+    Profiler &pf;
+    hipStream_t s;
+    StageMark(Profiler &p, hipStream_t st) : pf(p), s(st) {}
+    void begin(int st) { if (pf.on) (void)hipEventRecord(pf.ev[pf.pending][st][0], s); }
+    void end(int st) { if (pf.on) (void)hipEventRecord(pf.ev[pf.pending][st][1], s); }
+};
+
+// make every stage of a frame that skips it (full frames have no
+// prediction) record an empty interval
+void prof_begin_frame(Profiler &pf, hipStream_t s)
+{
+    if (!pf.on)
+        return;
+    if (pf.pending == kProfFrames)
+        (void)prof_flush(pf);
+    for (int st = 0; st < SGM_PROF_COUNT; st++) {
+        (void)hipEventRecord(pf.ev[pf.pending][st][0], s);
+        (void)hipEventRecord(pf.ev[pf.pending][st][1], s);
+    }
+}
+
+void prof_end_frame(Profiler &pf)
+{
+    if (pf.on)
+        pf.pending++;
+}
+
 // census, cost, aggregation, WTA (+ filter update in modes 0 and 1)
 int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, int mode, hipStream_t s)
 {
     const Geometry &g = ctx->g;
     DevBuffers &b = ctx->b;
+    StageMark mk(ctx->prof, s);
+    mk.begin(SGM_PROF_CENSUS);
     hipError_t e = launch_census(g, l, r, pitch, b.cen_l, b.cen_r, s);
+    mk.end(SGM_PROF_CENSUS);
     if (e != hipSuccess)
         return hip_fail(e, "census launch");
-    e = launch_cost(g, b, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "cost launch");
-    e = launch_aggregate(g, b, s);
+    if (ctx->debug) {
+        // the matching cost is computed inside the aggregation; the stand-alone
+        // cost kernel only materialises it for inspection
+        mk.begin(SGM_PROF_COST);
+        e = launch_cost(g, b, s);
+        mk.end(SGM_PROF_COST);
+        if (e != hipSuccess)
+            return hip_fail(e, "cost launch");
+    }
+    mk.begin(SGM_PROF_AGGREGATE);
+    e = launch_aggregate(g, b, mode == 0, s, ctx->side, ctx->fork, ctx->join);
+    mk.end(SGM_PROF_AGGREGATE);
     if (e != hipSuccess)
         return hip_fail(e, "aggregation launch");
+    mk.begin(SGM_PROF_WTA);
     e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, s);
+    mk.end(SGM_PROF_WTA);
     if (e != hipSuccess)
         return hip_fail(e, "wta launch");
     return SGM_OK;
@@ -264,6 +340,16 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
         delete ctx;
         return hip_fail(e, "initialisation");
     }
+    e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        free_buffers(b);
+        delete ctx;
+        return hip_fail(e, "stream/event creation");
+    }
     ctx->started = false;
     ctx->debug = false;
     *out = ctx;
@@ -275,8 +361,59 @@ void sgm_destroy(sgm_context *ctx)
     if (!ctx)
         return;
     (void)hipDeviceSynchronize();
+    (void)hipEventDestroy(ctx->fork);
+    (void)hipEventDestroy(ctx->join);
+    (void)hipStreamDestroy(ctx->side);
+    if (ctx->prof.created)
+        for (auto &f : ctx->prof.ev)
+            for (auto &st : f)
+                for (auto &ev : st)
+                    (void)hipEventDestroy(ev);
     free_buffers(ctx->b);
     delete ctx;
+}
+
+int sgm_set_profiling(sgm_context *ctx, int32_t on)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    Profiler &pf = ctx->prof;
+    if (on && !pf.created) {
+        for (auto &f : pf.ev)
+            for (auto &st : f)
+                for (auto &ev : st)
+                    if (hipEventCreate(&ev) != hipSuccess)
+                        return fail(SGM_EHIP, "event creation failed");
+        pf.created = true;
+    }
+    if (on) {
+        (void)hipDeviceSynchronize();
+        pf.pending = 0;
+        pf.frames = 0;
+        for (double &m : pf.ms)
+            m = 0.0;
+    }
+    pf.on = on != 0;
+    return SGM_OK;
+}
+
+int sgm_read_profile(sgm_context *ctx, double *ms, int64_t *frames, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!ms || !frames)
+        return fail(SGM_EINVAL, "output pointer is NULL");
+    hipError_t e = hipStreamSynchronize(as_stream(stream));
+    if (e == hipSuccess && ctx->prof.created)
+        e = prof_flush(ctx->prof);
+    if (e != hipSuccess)
+        return hip_fail(e, "profile read");
+    for (int i = 0; i < SGM_PROF_COUNT; i++)
+        ms[i] = ctx->prof.ms[i];
+    *frames = ctx->prof.frames;
+    return SGM_OK;
 }
 
 int sgm_set_debug(sgm_context *ctx, int32_t on)
@@ -293,12 +430,14 @@ int sgm_full_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *right, 
     if (rc || (rc = check_images(ctx, left, right, pitch)))
         return rc;
     hipStream_t s = as_stream(stream);
+    prof_begin_frame(ctx->prof, s);
     hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
     if (e != hipSuccess)
         return hip_fail(e, "window launch");
     rc = run_matcher(ctx, left, right, pitch, 0, s);
     if (rc)
         return rc;
+    prof_end_frame(ctx->prof);
     ctx->started = true;
     return SGM_OK;
 }
@@ -328,10 +467,18 @@ int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
     wc.zmin = 1e-9 * wc.fB;
     wc.q = p.q;
     hipStream_t s = as_stream(stream);
+    prof_begin_frame(ctx->prof, s);
+    StageMark mk(ctx->prof, s);
+    mk.begin(SGM_PROF_PREDICT);
     hipError_t e = launch_predict(ctx->g, ctx->b, wc, correct_const(p), s);
+    mk.end(SGM_PROF_PREDICT);
     if (e != hipSuccess)
         return hip_fail(e, "prediction launch");
-    return run_matcher(ctx, left, right, pitch, 1, s);
+    rc = run_matcher(ctx, left, right, pitch, 1, s);
+    if (rc)
+        return rc;
+    prof_end_frame(ctx->prof);
+    return SGM_OK;
 }
 
 int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
@@ -471,7 +618,10 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
     case SGM_STAGE_CENSUS_L: src = b.cen_l; need = N * 8; break;
     case SGM_STAGE_CENSUS_R: src = b.cen_r; need = N * 8; break;
     case SGM_STAGE_OFFSETS: src = b.off; need = (N + 1) * 4; break;
-    case SGM_STAGE_COST: src = b.cost; need = M; break;
+    case SGM_STAGE_COST:
+        if (!ctx->debug)
+            return fail(SGM_EINVAL, "SGM_STAGE_COST needs sgm_set_debug(ctx, 1) before the frame");
+        src = b.cost; need = M; break;
     case SGM_STAGE_SUM:
         if (!ctx->debug)
             return fail(SGM_EINVAL, "SGM_STAGE_SUM needs sgm_set_debug(ctx, 1) before the frame");

@@ -559,224 +559,564 @@ hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // Eq. 1 aggregation on ragged windows (Section 2.2).
-// One group of 16 lanes (a DPP row) walks one scanline of one path
-// direction; lanes hold consecutive disparities of the current pixel's
-// window (chunks of 16 for wider windows).  The predecessor's normalised
-// L_r lives in LDS indexed by absolute disparity (double-buffered per
-// group); a disparity outside the predecessor's window contributes nothing.
+//
+// A group of G lanes walks one scanline of one path direction.  Lanes map to
+// ABSOLUTE disparities: lane l of chunk j holds d = j*G + l, for the chunks
+// that intersect the current pixel's window.  The predecessor's L_r(q, d)
+// therefore stays in the same lane and register from one pixel to the next,
+// its neighbours d-1 and d+1 come from the adjacent lanes through DPP, and
+// the recurrence never touches memory:
 //   L_r(p,d) = C(p,d) + min(L(q,d), L(q,d-1)+P1, L(q,d+1)+P1, m_q+P2) - m_q
-// with q = p - r and m_q = min over q's window; the first pixel of a
-// scanline takes L_r = C.  Results are stored per path as bytes
+// with q = p - r and m_q the minimum over q's window; any term whose
+// disparity lies outside q's window is absent, and the first pixel of a
+// scanline takes L_r = C.  Register values outside the window they were
+// computed for are never read unmasked, so chunks a pixel does not touch
+// can keep stale values.  The matching cost C(p,d) = popcount(cL(p) xor
+// cR(x-d)) (the number of census bits when x-d < 0) is computed in place
+// from census strings staged in LDS; the cost volume never goes through
+// HBM.  Results are stored per path as bytes in the ragged layout
 // (L_r <= Nc + P2 <= 255, checked at create).
+//
+// Global loads are issued one batch ahead into registers that are read only
+// at the batch boundary, where they are written to LDS; the next pixel's
+// metadata and right census are read from LDS while the current pixel is
+// processed.
+//   k_agg_h: horizontal paths, one scanline (image row) per wave (G = 64);
+//            the row's right census is staged once, windows/offsets/left
+//            census stream through an LDS ring one batch ahead.
+//   k_agg_v: vertical and diagonal paths, G = 16 (a DPP row): 16 adjacent
+//            scanlines per block of four waves (adjacent columns, or adjacent
+//            diagonals, which cover a contiguous run of pixels at every row);
+//            each batch of rows stages the run's census strings, windows,
+//            offsets and the right-census span it can match against.
 // ---------------------------------------------------------------------------
 
-constexpr int AGG_G = 16, AGG_WAVES = 1, AGG_GROUPS = 4 * AGG_WAVES, AGG_T = 64 * AGG_WAVES;
-
 struct AggArgs {
-    const uint8_t *cost;
+    const uint64_t *cl, *cr;
     const uint16_t *win;
     const uint32_t *off;
     uint8_t *lr;
     size_t lr_stride;
-    int W, H, p1, p2, npaths;
+    int W, H, D, nbits, p1, p2;
     int8_t rx[kMaxPaths], ry[kMaxPaths];
+    int8_t slot[kMaxPaths];   // output buffer index of each listed path
+    int kmin[kMaxPaths];      // first chain index of each listed path (k_agg_v)
 };
 
-template <int MAXCH>
-__global__ __launch_bounds__(AGG_T) void k_aggregate(AggArgs a)
-{
-    __shared__ uint16_t buf[AGG_GROUPS][2][kMaxDisp + 2];
-    const int k = blockIdx.y;
-    const int grp = threadIdx.x >> 4, lane = threadIdx.x & 15;
-    const int chain = blockIdx.x * AGG_GROUPS + grp;
-    const int W = a.W, H = a.H;
-    const int rx = a.rx[k], ry = a.ry[k];
-    const int nch = (ry == 0) ? H : (rx == 0) ? W : W + H - 1;
-    if (chain >= nch)
-        return;
-    // first pixel of the scanline and its length
-    const int xs = rx > 0 ? 0 : W - 1, ys = ry > 0 ? 0 : H - 1;
-    int x, y;
-    if (ry == 0) {
-        x = xs;
-        y = chain;
-    } else if (rx == 0) {
-        x = chain;
-        y = ys;
-    } else if (chain < W) {
-        x = chain;
-        y = ys;
-    } else {
-        x = xs;
-        y = ys + ry * (chain - W + 1);
-    }
-    int len;
-    {
-        int lx = rx > 0 ? W - x : (rx < 0 ? x + 1 : 1 << 30);
-        int ly = ry > 0 ? H - y : (ry < 0 ? y + 1 : 1 << 30);
-        len = min(lx, ly);
-    }
-    const int step = ry * W + rx;
-    int p = y * W + x;
-    uint8_t *lrk = a.lr + (size_t)k * a.lr_stride;
-    uint16_t *bA = buf[grp][0];
-    uint16_t *bB = buf[grp][1];
-    const int p1 = a.p1, p2 = a.p2;
-    int mq = 0, loq = 0, hiq = -1;
+constexpr int LBIG = 0x3FFF;   // "absent" predecessor term (> any L_r + P1)
 
-    // software pipeline: window/offset and costs of the next pixel are
-    // loaded while the current one is processed
-    uint32_t o = a.off[p];
-    uint32_t wv = a.win[p];
-    int cst[MAXCH];
-    {
-        int w = (int)(wv >> 8) + 1;
-#pragma unroll
-        for (int j = 0; j < MAXCH; j++)
-            if (j * AGG_G + lane < w)
-                cst[j] = a.cost[o + j * AGG_G + lane];
+// DPP move: row_shr:1 (0x111) / wave_shr:1 (0x138) give lane i the value of
+// lane i-1, row_shl:1 (0x101) / wave_shl:1 (0x130) that of lane i+1,
+// row_ror:n (0x120+n) that of lane (i-n) mod 16 of the same row; lanes
+// without a source receive LBIG.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(LBIG, v, CTRL, 0xF, 0xF, false);
+}
+
+// lane i <- lane i-1 / i+1 of the same group (the group's first / last lane
+// receives LBIG and is patched by the caller)
+template <int G>
+__device__ __forceinline__ int from_prev_lane(int v) { return G == 64 ? dpp<0x138>(v) : dpp<0x111>(v); }
+template <int G>
+__device__ __forceinline__ int from_next_lane(int v) { return G == 64 ? dpp<0x130>(v) : dpp<0x101>(v); }
+
+// min over a group of G lanes, result in every lane of the group
+template <int G>
+__device__ __forceinline__ int group_min(int v)
+{
+    v = row_min16(v);
+    if (G == 64) {
+        int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+        int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+        v = min(min(a, b), min(c, d));
     }
-    for (int i = 0; i < len; i++) {
-        const int lo = (int)(wv & 255), w = (int)(wv >> 8) + 1, hi = lo + w - 1;
-        const uint32_t oc = o;
-        int cur[MAXCH];
+    return v;
+}
+
+// min / max of a group-uniform value over the four 16-lane groups of a wave
+__device__ __forceinline__ int wave_min4(int v)
+{
+    int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return min(min(a, b), min(c, d));
+}
+__device__ __forceinline__ int wave_max4(int v)
+{
+    int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
+    int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
+    return max(max(a, b), max(c, d));
+}
+
+// Per-group recurrence state: L_r of the previous pixel by absolute
+// disparity, LBIG outside its window (so absent terms need no test), and
+// its minimum.
+template <int MAXCH>
+struct Chain {
+    int Lp[MAXCH];
+    int mq;
+};
+
+// right census needed by chunk j at column x (crow[i] holds column crow_x0+i;
+// x-d < 0 reads entry 0 and is replaced by the fixed cost)
+template <int G, int MAXCH>
+__device__ __forceinline__ void read_crow(uint64_t (&crv)[MAXCH], const uint64_t *crow, int crow_x0, int x, int lane,
+                                          int jlo, int jhi)
+{
 #pragma unroll
-        for (int j = 0; j < MAXCH; j++)
-            cur[j] = cst[j];
-        if (i + 1 < len) {
-            const int pn = p + step;
-            o = a.off[pn];
-            wv = a.win[pn];
-            const int wn = (int)(wv >> 8) + 1;
-#pragma unroll
-            for (int j = 0; j < MAXCH; j++)
-                if (j * AGG_G + lane < wn)
-                    cst[j] = a.cost[o + j * AGG_G + lane];
-            p = pn;
-        }
-        int rmin = 0x7FFF;
-#pragma unroll
-        for (int j = 0; j < MAXCH; j++) {
-            const int sidx = j * AGG_G + lane;
-            if (sidx < w) {
-                const int d = lo + sidx;
-                int L;
-                if (i == 0) {
-                    L = cur[j];
-                } else {
-                    int best = mq + p2;
-                    const int v0 = bA[d + 1], vm = bA[d], vp = bA[d + 2];
-                    if (d >= loq && d <= hiq)
-                        best = min(best, v0);
-                    if (d - 1 >= loq && d - 1 <= hiq)
-                        best = min(best, vm + p1);
-                    if (d + 1 >= loq && d + 1 <= hiq)
-                        best = min(best, vp + p1);
-                    L = cur[j] + best - mq;
-                }
-                bB[d + 1] = (uint16_t)L;
-                lrk[oc + sidx] = (uint8_t)L;
-                rmin = min(rmin, L);
-            }
-        }
-        mq = row_min16(rmin);
-        loq = lo;
-        hiq = hi;
-        uint16_t *t = bA;
-        bA = bB;
-        bB = t;
-        wave_lds_sync();
+    for (int j = 0; j < MAXCH; j++) {
+        if (j < jlo || j > jhi)
+            continue;
+        const int d = j * G + lane;
+        crv[j] = crow[max(x - d - crow_x0, 0)];
     }
 }
 
-hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, hipStream_t s)
+// every chunk, unconditionally: a fixed number of LDS reads per step keeps
+// the wait counters exact, so a read issued for the next step is not waited
+// for in this one
+template <int G, int MAXCH>
+__device__ __forceinline__ void read_crow_all(uint64_t (&crv)[MAXCH], const uint64_t *crow, int x, int lane)
 {
-    AggArgs a;
-    a.cost = b.cost;
-    a.win = b.win;
-    a.off = b.off;
-    a.lr = b.lr;
-    a.lr_stride = (size_t)g.N * g.D;
-    a.W = g.W;
-    a.H = g.H;
-    a.p1 = g.p1;
-    a.p2 = g.p2;
-    a.npaths = g.npaths;
-    for (int k = 0; k < kMaxPaths; k++) {
-        a.rx[k] = g.rx[k];
-        a.ry[k] = g.ry[k];
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++)
+        crv[j] = crow[max(x - (j * G + lane), 0)];
+}
+
+// min over the G lanes of a group with DPP, result in every lane of the group
+template <int G>
+__device__ __forceinline__ int group_min_dpp(int v)
+{
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false));   // row_ror:8
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x124, 0xF, 0xF, false));   // row_ror:4
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x122, 0xF, 0xF, false));   // row_ror:2
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x121, 0xF, 0xF, false));   // row_ror:1
+    if (G == 64) {
+        // every lane holds its row's minimum: combine the four rows
+        v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15 -> rows 1, 3
+        v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31 -> rows 2, 3
+        v = __builtin_amdgcn_readlane(v, 63);
     }
-    int maxch = g.W + g.H - 1;
-    dim3 grd((maxch + AGG_GROUPS - 1) / AGG_GROUPS, g.npaths), blk(AGG_T);
-    if (g.D <= 64)
-        hipLaunchKernelGGL(k_aggregate<4>, grd, blk, 0, s, a);
-    else if (g.D <= 128)
-        hipLaunchKernelGGL(k_aggregate<8>, grd, blk, 0, s, a);
-    else
-        hipLaunchKernelGGL(k_aggregate<16>, grd, blk, 0, s, a);
-    return hipGetLastError();
+    return v;
+}
+
+// One step of Eq. 1 for this group's pixel (column x, window [lo, hi],
+// ragged offset oc).  Chunks jlo..jhi (uniform over the wave) are computed,
+// the others are reset to LBIG; `active`: this group has a pixel at this
+// step (uniform per group).
+template <int G, int MAXCH>
+__device__ __forceinline__ void agg_step(Chain<MAXCH> &st, int lane, bool active, bool first, uint64_t clp, int x,
+                                         int lo, int hi, uint32_t oc, const uint64_t (&crv)[MAXCH], int jlo, int jhi,
+                                         int p1, int p2, int nbits, uint8_t *lrk)
+{
+    int Ln[MAXCH];
+    int rmin = LBIG;
+    const int mq = st.mq;
+    const int cap = first ? LBIG : mq + p2;    // the P2 term (none on the first pixel)
+    const int base = first ? 0 : -mq;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++) {
+        Ln[j] = LBIG;
+        if (j < jlo || j > jhi)
+            continue;
+        const int d = j * G + lane;
+        // neighbours at d-1 and d+1 in the previous pixel's registers
+        int pm = from_prev_lane<G>(st.Lp[j]);
+        int pp = from_next_lane<G>(st.Lp[j]);
+        if (j > 0) {
+            const int edge = G == 64 ? __builtin_amdgcn_readlane(st.Lp[j - 1], 63) : dpp<0x121>(st.Lp[j - 1]);
+            pm = lane == 0 ? edge : pm;
+        }
+        if (j < MAXCH - 1) {
+            const int edge = G == 64 ? __builtin_amdgcn_readlane(st.Lp[j + 1], 0) : dpp<0x12F>(st.Lp[j + 1]);
+            pp = lane == G - 1 ? edge : pp;
+        }
+        const int best = first ? 0 : min(min(st.Lp[j], cap), min(pm, pp) + p1);
+        const int c = d > x ? nbits : __popcll(clp ^ crv[j]);
+        const int L = c + best + base;
+        const bool in = active && (unsigned)(d - lo) <= (unsigned)(hi - lo);
+        Ln[j] = in ? L : LBIG;
+        rmin = min(rmin, Ln[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++) {
+        if (j < jlo || j > jhi)
+            continue;
+        const int d = j * G + lane;
+        if (Ln[j] != LBIG)
+            lrk[oc + (uint32_t)(d - lo)] = (uint8_t)Ln[j];
+    }
+    const int m = group_min_dpp<G>(rmin);
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < MAXCH; j++)
+            st.Lp[j] = Ln[j];
+        st.mq = m;
+    }
+}
+
+struct MetaEntry {
+    uint64_t cl;
+    uint32_t off, win;
+};
+
+// ---- horizontal paths: one scanline per wave ------------------------------
+
+constexpr int AH_B = 64;   // batch of pixels per metadata load (one per lane)
+
+__host__ __device__ constexpr size_t agg_h_lds(int W) { return (size_t)W * 8; }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int MAXCH>
+__global__ __launch_bounds__(64) void k_agg_h(AggArgs a)
+{
+    constexpr int G = 64;
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int W = a.W;
+    uint64_t *crow = (uint64_t *)smem;   // [W]
+    const int pi = blockIdx.y;
+    const int k = a.slot[pi];
+    const int rx = a.rx[pi];
+    const int lane = threadIdx.x;
+    const int row = blockIdx.x;
+    const int rowp = row * W;
+    // stage the row's right census
+    {
+        const uint64_t *src = a.cr + (size_t)rowp;
+        if ((rowp & 1) == 0) {
+            const uint4 *s4 = (const uint4 *)src;
+            uint4 *d4 = (uint4 *)crow;
+#pragma unroll 8
+            for (int i = lane; i < W / 2; i += 64)
+                d4[i] = s4[i];
+            if ((W & 1) && lane == 0)
+                crow[W - 1] = src[W - 1];
+        } else {
+#pragma unroll 8
+            for (int i = lane; i < W; i += 64)
+                crow[i] = src[i];
+        }
+    }
+    // metadata batches live in registers, one pixel per lane
+    auto px = [&](int t) { return rowp + (rx > 0 ? t : W - 1 - t); };
+    uint64_t bcl;
+    uint32_t boff, bwin;
+    {
+        const int p = px(min(lane, W - 1));
+        bcl = a.cl[p];
+        boff = a.off[p];
+        bwin = a.win[p];
+    }
+    __syncthreads();
+    uint8_t *lrk = a.lr + (size_t)k * a.lr_stride;
+    const int p1 = a.p1, p2 = a.p2, nbits = a.nbits;
+    Chain<MAXCH> st;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++)
+        st.Lp[j] = LBIG;
+    st.mq = 0;
+    uint64_t crvA[MAXCH], crvB[MAXCH];
+    read_crow_all<G, MAXCH>(crvA, crow, rx > 0 ? 0 : W - 1, lane);   // pixel 0's right census
+    // one step: pixel t (metadata from lane s of the batch registers) with
+    // census `cur`; the census of pixel t+1 is read into `nxt`
+    auto step = [&](int t, int s, uint64_t nb_cl, uint32_t nb_off, uint32_t nb_win, uint64_t(&cur)[MAXCH],
+                    uint64_t(&nxt)[MAXCH]) {
+        const uint64_t cl = readlane64(bcl, s);
+        const uint32_t off = (uint32_t)__builtin_amdgcn_readlane((int)boff, s);
+        const uint32_t win = (uint32_t)__builtin_amdgcn_readlane((int)bwin, s);
+        read_crow_all<G, MAXCH>(nxt, crow, rx > 0 ? min(t + 1, W - 1) : max(W - 2 - t, 0), lane);
+        const int lo = (int)(win & 255), hi = lo + (int)(win >> 8);
+        agg_step<G, MAXCH>(st, lane, true, t == 0, cl, rx > 0 ? t : W - 1 - t, lo, hi, off, cur, lo / G, hi / G,
+                           p1, p2, nbits, lrk);
+        (void)nb_cl;
+        (void)nb_off;
+    };
+    const int nb = (W + AH_B - 1) / AH_B;
+    for (int b = 0; b < nb; b++) {
+        // next batch, requested a batch ahead
+        const int p = px(min((b + 1) * AH_B + lane, W - 1));
+        const uint64_t ncl = a.cl[p];
+        const uint32_t noff = a.off[p], nwin = a.win[p];
+        const int steps = min(AH_B, W - b * AH_B);
+        int s = 0;
+        for (; s + 1 < steps; s += 2) {
+            step(b * AH_B + s, s, ncl, noff, nwin, crvA, crvB);
+            step(b * AH_B + s + 1, s + 1, ncl, noff, nwin, crvB, crvA);
+        }
+        if (s < steps) {
+            // odd tail (last batch only): one step, then the census is in B
+            step(b * AH_B + s, s, ncl, noff, nwin, crvA, crvB);
+#pragma unroll
+            for (int j = 0; j < MAXCH; j++)
+                crvA[j] = crvB[j];
+        }
+        bcl = ncl;
+        boff = noff;
+        bwin = nwin;
+    }
+}
+
+// ---- vertical and diagonal paths ------------------------------------------
+
+constexpr int AV_G = 16, AV_NG = 16, AV_T = AV_G * AV_NG, AV_B = 8;
+
+__host__ __device__ constexpr int agg_v_span(int D) { return AV_NG + D - 1; }
+
+__host__ __device__ constexpr size_t agg_v_lds(int D)
+{
+    return (size_t)2 * AV_B * agg_v_span(D) * 8 + (size_t)2 * AV_B * AV_NG * sizeof(MetaEntry);
+}
+
+// loads of one batch of rows held in registers between issue and LDS write
+constexpr int AV_MAXCR = (AV_B * (AV_NG + kMaxDisp - 1) + AV_T - 1) / AV_T;   // per thread
+
+template <int MAXCH>
+__global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int W = a.W, H = a.H, D = a.D;
+    const int span = AV_NG + D - 1;
+    uint64_t *cbuf = (uint64_t *)smem;                                            // [2][B][span]
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AV_B * span * 8);          // [2][B][NG]
+    const int pi = blockIdx.y;
+    const int k = a.slot[pi];
+    const int rx = a.rx[pi], ry = a.ry[pi];
+    const int kmin = a.kmin[pi];
+    const int nchains = rx == 0 ? W : W + H - 1;
+    if (blockIdx.x * AV_NG >= nchains)
+        return;                                        // uniform over the block
+    const int kb = kmin + blockIdx.x * AV_NG;          // chain index of group 0
+    const int grp = threadIdx.x / AV_G, lane = threadIdx.x % AV_G;
+    const int kc = kb + grp;
+    const bool chain_ok = blockIdx.x * AV_NG + grp < nchains;
+    const int ys = ry > 0 ? 0 : H - 1;
+    uint8_t *lrk = a.lr + (size_t)k * a.lr_stride;
+    const int p1 = a.p1, p2 = a.p2, nbits = a.nbits;
+
+    // sweep row t: y = ys + ry*t, chain kc sits at x = kc + rx*t.  The block's
+    // run is x in [kb + rx*t, kb + NG-1 + rx*t]; its matching span starts
+    // D-1 columns left of the run.
+    auto span_x0 = [&](int t) { return kb + rx * t - (D - 1); };
+
+    uint64_t rc[AV_MAXCR];
+    uint64_t rmcl;
+    uint32_t rmoff, rmwin;
+    auto issue = [&](int bt) {
+#pragma unroll
+        for (int i = 0; i < AV_MAXCR; i++) {
+            const int e = threadIdx.x + i * AV_T;
+            const int r = e / span, c = e - r * span;
+            const int t = bt * AV_B + r;
+            const int xx = span_x0(t) + c;
+            const bool ok = r < AV_B && t < H && xx >= 0 && xx < W;
+            const size_t idx = ok ? (size_t)(ys + ry * t) * W + xx : 0;
+            const uint64_t v = a.cr[idx];
+            rc[i] = ok ? v : 0ull;
+        }
+        {
+            const int e = threadIdx.x;   // AV_B * AV_NG = 128 entries
+            const int r = e / AV_NG, g = e - r * AV_NG;
+            const int t = bt * AV_B + r;
+            const int xx = kb + g + rx * t;
+            const bool ok = e < AV_B * AV_NG && t < H && xx >= 0 && xx < W;
+            const int pix = ok ? (ys + ry * t) * W + xx : 0;
+            const uint64_t vcl = a.cl[pix];
+            const uint32_t voff = a.off[pix], vwin = a.win[pix];
+            rmcl = ok ? vcl : 0ull;
+            rmoff = ok ? voff : 0u;
+            rmwin = ok ? vwin : 0u;
+        }
+    };
+    auto commit = [&](int buf) {
+        uint64_t *cb = cbuf + (size_t)buf * AV_B * span;
+#pragma unroll
+        for (int i = 0; i < AV_MAXCR; i++) {
+            const int e = threadIdx.x + i * AV_T;
+            if (e < AV_B * span)
+                cb[e] = rc[i];
+        }
+        if (threadIdx.x < AV_B * AV_NG) {
+            MetaEntry m;
+            m.cl = rmcl;
+            m.off = rmoff;
+            m.win = rmwin;
+            mbuf[buf * AV_B * AV_NG + threadIdx.x] = m;
+        }
+    };
+    issue(0);
+    commit(0);
+    __syncthreads();
+    Chain<MAXCH> st;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++)
+        st.Lp[j] = LBIG;
+    st.mq = 0;
+    bool started = false;
+    const int nbt = (H + AV_B - 1) / AV_B;
+    for (int bt = 0; bt < nbt; bt++) {
+        issue(bt + 1);
+        const uint64_t *cb = cbuf + (size_t)(bt & 1) * AV_B * span;
+        const MetaEntry *mb = mbuf + (bt & 1) * AV_B * AV_NG;
+        const int rows = min(AV_B, H - bt * AV_B);
+        for (int r = 0; r < rows; r++) {
+            const int t = bt * AV_B + r;
+            const int x = kc + rx * t;
+            const bool act = chain_ok && x >= 0 && x < W;   // uniform per group
+            const MetaEntry e = mb[r * AV_NG + grp];
+            const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
+            // chunks touched by any active group of the wave
+            const int jlo = wave_min4(act ? lo / AV_G : MAXCH);
+            const int jhi = wave_max4(act ? hi / AV_G : -1);
+            if (jlo <= jhi) {
+                uint64_t crv[MAXCH];
+                read_crow<AV_G, MAXCH>(crv, cb + (size_t)r * span, span_x0(t), x, lane, jlo, jhi);
+                agg_step<AV_G, MAXCH>(st, lane, act, !started, e.cl, x, lo, hi, e.off, crv, jlo, jhi, p1, p2, nbits,
+                                      lrk);
+                started = started || act;
+            }
+        }
+        // buffer (bt+1)&1 was last read in batch bt-1, which the previous
+        // barrier closed; this barrier publishes it for batch bt+1
+        commit((bt + 1) & 1);
+        __syncthreads();
+    }
+}
+
+hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, bool full_range, hipStream_t s, hipStream_t side,
+                            hipEvent_t fork, hipEvent_t join)
+{
+    (void)full_range;
+    AggArgs hv, vv;
+    for (AggArgs *a : {&hv, &vv}) {
+        a->cl = b.cen_l;
+        a->cr = b.cen_r;
+        a->win = b.win;
+        a->off = b.off;
+        a->lr = b.lr;
+        a->lr_stride = (size_t)g.N * g.D;
+        a->W = g.W;
+        a->H = g.H;
+        a->D = g.D;
+        a->nbits = g.nbits;
+        a->p1 = g.p1;
+        a->p2 = g.p2;
+    }
+    int nh = 0, nv = 0;
+    int maxv = 0;
+    for (int k = 0; k < g.npaths; k++) {
+        if (g.ry[k] == 0) {
+            hv.rx[nh] = g.rx[k];
+            hv.ry[nh] = 0;
+            hv.slot[nh] = (int8_t)k;
+            nh++;
+        } else {
+            vv.rx[nv] = g.rx[k];
+            vv.ry[nv] = g.ry[k];
+            vv.slot[nv] = (int8_t)k;
+            // chain index range: x = kc + rx*t over t in [0, H)
+            vv.kmin[nv] = g.rx[k] > 0 ? -(g.H - 1) : 0;
+            maxv = max(maxv, g.rx[k] == 0 ? g.W : g.W + g.H - 1);
+            nv++;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (nh) {
+        e = hipEventRecord(fork, s);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(side, fork, 0);
+        if (e != hipSuccess)
+            return e;
+        size_t lds = agg_h_lds(g.W);
+        dim3 grd(g.H, nh);
+        if (g.D <= 64)
+            hipLaunchKernelGGL((k_agg_h<1>), grd, dim3(64), lds, side, hv);
+        else if (g.D <= 128)
+            hipLaunchKernelGGL((k_agg_h<2>), grd, dim3(64), lds, side, hv);
+        else
+            hipLaunchKernelGGL((k_agg_h<4>), grd, dim3(64), lds, side, hv);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (nv) {
+        size_t lds = agg_v_lds(g.D);
+        dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
+        if (g.D <= 64)
+            hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
+        else if (g.D <= 128)
+            hipLaunchKernelGGL((k_agg_v<8>), grd, dim3(AV_T), lds, s, vv);
+        else
+            hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    if (nh) {
+        e = hipEventRecord(join, side);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, join, 0);
+    }
+    return e;
 }
 
 // ---------------------------------------------------------------------------
 // winner-takes-all (Section 2.3) with parabolic sub-pixel fit, then the
 // Kalman correction (Eq. 5-6) and the innovation test (Section 4).
-// Pass 1 (all threads, coalesced over the block's cell range): S = sum of
-// the paths' L_r; per-pixel argmin via an LDS atomic on (S << 9 | slot),
-// which picks the smallest S and then the lowest disparity.  Pass 2 (one
-// thread per pixel): sub-pixel fit and filter update in double precision.
+// A group of 16 lanes (a DPP row) handles one pixel: lanes sum the paths'
+// L_r over the window (S), keep S in LDS and reduce (S << 9 | slot), which
+// picks the smallest S and then the lowest disparity.  Lane 0 then fits the
+// parabola through S(d*-1), S(d*), S(d*+1) and updates the filter in double
+// precision.
 // ---------------------------------------------------------------------------
 
-constexpr int WTA_PIX = 256;
+constexpr int WTA_G = 16, WTA_NG = 16, WTA_T = WTA_G * WTA_NG;
 
-__global__ __launch_bounds__(WTA_PIX) void k_wta_correct(int N, int D, int npaths, CorrectConst cc, int mode,
-                                                         const uint8_t *__restrict__ lr, size_t lr_stride,
-                                                         const uint16_t *__restrict__ win,
-                                                         const uint32_t *__restrict__ off,
-                                                         const uint8_t *__restrict__ flags,
-                                                         const double *__restrict__ dhat,
-                                                         const double *__restrict__ pm, uint16_t *__restrict__ dbg_sum,
-                                                         int32_t *__restrict__ dstar_out, double *__restrict__ dz_out,
-                                                         double *__restrict__ d_state, double *__restrict__ p_state,
-                                                         uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags)
+__global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths, CorrectConst cc, int mode,
+                                                       const uint8_t *__restrict__ lr, size_t lr_stride,
+                                                       const uint16_t *__restrict__ win,
+                                                       const uint32_t *__restrict__ off,
+                                                       const uint8_t *__restrict__ flags,
+                                                       const double *__restrict__ dhat,
+                                                       const double *__restrict__ pm, uint16_t *__restrict__ dbg_sum,
+                                                       int32_t *__restrict__ dstar_out, double *__restrict__ dz_out,
+                                                       double *__restrict__ d_state, double *__restrict__ p_state,
+                                                       uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags)
 {
-    __shared__ uint32_t soff[WTA_PIX];
-    __shared__ uint32_t skey[WTA_PIX];
-    const int p0 = blockIdx.x * WTA_PIX;
-    const int np = min(WTA_PIX, N - p0);
-    if ((int)threadIdx.x < np) {
-        soff[threadIdx.x] = off[p0 + threadIdx.x];
-        skey[threadIdx.x] = 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    const uint32_t c0 = soff[0], c1 = off[p0 + np];
-    for (uint32_t c = c0 + threadIdx.x; c < c1; c += WTA_PIX) {
-        int i = find_pixel(soff, np, c);
+    __shared__ uint16_t ssum[WTA_NG][kMaxDisp];
+    const int grp = threadIdx.x / WTA_G, lane = threadIdx.x % WTA_G;
+    const int t = blockIdx.x * WTA_NG + grp;
+    if (t >= N)
+        return;   // the whole group leaves together
+    const uint32_t o = off[t];
+    const uint32_t wv = win[t];
+    const int lo = (int)(wv & 255), w = (int)(wv >> 8) + 1, hi = lo + w - 1;
+    uint32_t key = 0x7FFFFFFFu;   // above every real key (S << 9 | slot < 2^20)
+    for (int sl = lane; sl < w; sl += WTA_G) {
         uint32_t sv = 0;
         for (int k = 0; k < npaths; k++)
-            sv += lr[(size_t)k * lr_stride + c];
+            sv += lr[(size_t)k * lr_stride + o + sl];
+        ssum[grp][sl] = (uint16_t)sv;
         if (dbg_sum)
-            dbg_sum[c] = (uint16_t)sv;
-        atomicMin(&skey[i], (sv << 9) | (c - soff[i]));
+            dbg_sum[o + sl] = (uint16_t)sv;
+        key = min(key, (sv << 9) | (uint32_t)sl);
     }
-    __syncthreads();
-    if ((int)threadIdx.x >= np)
+    key = (uint32_t)row_min16((int)key);   // keys < 2^31: the signed min is the unsigned min
+    wave_lds_sync();
+    if (lane != 0)
         return;
-    const int t = p0 + threadIdx.x;
-    const uint32_t key = skey[threadIdx.x];
     const int slot = (int)(key & 511u);
     const int s0 = (int)(key >> 9);
-    const uint32_t wv = win[t];
-    const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
     const int ds = lo + slot;
     double dz = (double)ds;
     if (ds - 1 >= lo && ds + 1 <= hi) {
-        const uint32_t c = soff[threadIdx.x] + (uint32_t)slot;
-        int sm = 0, sp = 0;
-        for (int k = 0; k < npaths; k++) {
-            sm += lr[(size_t)k * lr_stride + c - 1];
-            sp += lr[(size_t)k * lr_stride + c + 1];
-        }
-        const int a = sm - s0, b = sp - s0;
+        const int a = (int)ssum[grp][slot - 1] - s0, b = (int)ssum[grp][slot + 1] - s0;
         dz = (double)ds + (double)(a - b) / (double)(2 * (a + b));
     }
     dstar_out[t] = ds;
@@ -809,8 +1149,8 @@ __global__ __launch_bounds__(WTA_PIX) void k_wta_correct(int N, int D, int npath
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
                               bool debug_sum, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wta_correct, dim3((g.N + WTA_PIX - 1) / WTA_PIX), dim3(WTA_PIX), 0, s, g.N, g.D,
-                       g.npaths, cc, mode, b.lr, (size_t)g.N * g.D, b.win, b.off, b.flags, b.dhat, b.pm,
+    hipLaunchKernelGGL(k_wta_correct, dim3((g.N + WTA_NG - 1) / WTA_NG), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
+                       mode, b.lr, (size_t)g.N * g.D, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags);
     return hipGetLastError();
 }
