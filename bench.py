@@ -29,12 +29,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "frames/s and cost-cells/s, reduced vs full SGM at 1242×375×128, 1 GPU"
-# algorithmic bytes of the aggregation schedule:
-# per cell and path: read the cost byte, write the path-loss byte;
-# per pixel and path: read the ragged offset (4 B) and window (2 B)
-AGG_BYTES_PER_CELL_PATH = 2
-AGG_BYTES_PER_PIXEL_PATH = 6
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_aggregate_driving.txt")
+# Algorithmic bytes per launch ("Roofline"):
+#  aggregation, per path: read left+right census (16 B), window (2 B) and
+#  ragged offset (4 B) of every pixel, write one path-loss byte per cell;
+#  WTA + correction: read every path's byte per cell; per pixel read window,
+#  offset, flags, prediction (23 B) and write state, mask, flags, d*, d_z (30 B).
+AGG_BYTES_PER_PIXEL_PATH = 22
+AGG_BYTES_PER_CELL_PATH = 1
+WTA_BYTES_PER_PIXEL = 53
+KERNEL_NAMES = {"agg_h": "k_agg_h (Eq. 1, horizontal paths)", "agg_v": "k_agg_v (Eq. 1, vertical + diagonal paths)",
+                "wta": "k_wta_correct (WTA, sub-pixel, Kalman, chi2)"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_driving.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_07986_amd", "csrc", "sgm_kernels.hip")
 
 
@@ -62,22 +67,33 @@ def source_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic():
-    """Per-launch HBM bytes of the aggregation kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None, None
+def read_traffic(kernel: str):
+    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    path = TRAFFIC_FILE.format(kernel=kernel)
+    if not os.path.exists(path):
+        return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
-        if "=" in line and not line.startswith("#"):
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     if kv.get("source_sha") != source_sha():
-        return None, kv.get("source_sha")
+        return None
     try:
-        return float(kv["bytes_per_launch"]), kv.get("source_sha")
+        return float(kv["bytes_per_launch"])
     except (KeyError, ValueError):
-        return None, None
+        return None
+
+
+def algorithmic_bytes(stage: str, n_px: int, cells: float, npaths_h: int = 2, npaths_v: int = 6):
+    if stage == "agg_h":
+        return npaths_h * (AGG_BYTES_PER_PIXEL_PATH * n_px + AGG_BYTES_PER_CELL_PATH * cells)
+    if stage == "agg_v":
+        return npaths_v * (AGG_BYTES_PER_PIXEL_PATH * n_px + AGG_BYTES_PER_CELL_PATH * cells)
+    if stage == "wta":
+        return (npaths_h + npaths_v) * cells + WTA_BYTES_PER_PIXEL * n_px
+    return None
 
 
 def cpu_baseline(seq, frames: int):
@@ -106,6 +122,7 @@ def main():
     ap.add_argument("--full-steps", type=int, default=100)
     ap.add_argument("--cpu-frames", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--skip-full", action="store_true", help="skip the full-range comparison (profiling runs)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -191,41 +208,45 @@ def main():
     stage_avg = {k: v / max(nprof, 1) for k, v in stage_ms.items()}
 
     # ---- full-range SGM on the same frames --------------------------------
-    gf = sgmk.ReducedSGM(W, H, D, **params)
-    for i in range(5):
-        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.full_steps):
-        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
-    torch.cuda.synchronize()
-    dtf = time.perf_counter() - t0
-    full_fps = args.full_steps / dtf
-    gf.set_profiling(True)
-    for i in range(args.full_steps):
-        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
-    full_stage_ms, nf = gf.read_profile()
-    full_bad = 0
-    for k in range(1, seq.frames):
-        gf.full_frame(Ls[k], Rs[k])
-        v = torch.from_numpy(seq.valid[k]).to(dev)
-        gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).to(dev)
-        full_bad += int(((gf.disparity() - gt).abs() > 3)[v].sum())
-    gf.close()
+    full = None
+    if not args.skip_full:
+        gf = sgmk.ReducedSGM(W, H, D, **params)
+        for i in range(5):
+            gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.full_steps):
+            gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+        torch.cuda.synchronize()
+        dtf = time.perf_counter() - t0
+        full_fps = args.full_steps / dtf
+        gf.set_profiling(True)
+        for i in range(args.full_steps):
+            gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+        full_stage_ms, nf = gf.read_profile()
+        full_bad = 0
+        for k in range(1, seq.frames):
+            gf.full_frame(Ls[k], Rs[k])
+            v = torch.from_numpy(seq.valid[k]).to(dev)
+            gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).to(dev)
+            full_bad += int(((gf.disparity() - gt).abs() > 3)[v].sum())
+        gf.close()
+        full = {"frames_per_s": round(full_fps, 2), "ms_per_frame": round(dtf / args.full_steps * 1e3, 4),
+                "cost_cells_per_s": round(full_fps * H * W * D, 1),
+                "stage_ms": {k: round(v / max(nf, 1), 5) for k, v in full_stage_ms.items()},
+                "bad_px_gt3": round(full_bad / max(nval, 1), 6)}
 
     # ---- roofline of the dominant kernel ---------------------------------
-    dom = max(stage_avg, key=stage_avg.get)
-    npaths = 8
     mean_cells = timed_cells / args.steps
-    agg_bytes = npaths * (AGG_BYTES_PER_CELL_PATH * mean_cells + AGG_BYTES_PER_PIXEL_PATH * H * W)
-    agg_ms = stage_avg["aggregate"]
-    achieved = agg_bytes / (agg_ms * 1e-3) / 1e9
-    traffic, traffic_sha = read_traffic()
-    roofline = {"bound": "hbm", "kernel": "k_aggregate (8-path Eq. 1 aggregation)",
+    kern = {k: v for k, v in stage_avg.items() if k in KERNEL_NAMES}
+    dom = max(kern, key=kern.get)
+    dom_bytes = algorithmic_bytes(dom, H * W, mean_cells)
+    dom_ms = kern[dom]
+    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "algorithmic_bytes_per_launch": int(agg_bytes), "avg_launch_ms": round(agg_ms, 5),
-                "dominant_stage": dom}
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom),
+                "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_ms, 5)}
 
     out = {
         "metric": METRIC,
@@ -245,15 +266,14 @@ def main():
                    "state_dtype": "f64", "cost_dtype": "u8", "path_loss_dtype": "u8", "sum_dtype": "u16"},
         "cost_cells_per_s": round(timed_cells / dt, 1),
         "mean_cells_per_frame": round(mean_cells, 1),
+        "kernel_source_sha": source_sha(),
         "full_cells_per_frame": H * W * D,
-        "full_range": {"frames_per_s": round(full_fps, 2), "ms_per_frame": round(dtf / args.full_steps * 1e3, 4),
-                       "cost_cells_per_s": round(full_fps * H * W * D, 1),
-                       "stage_ms": {k: round(v / max(nf, 1), 5) for k, v in full_stage_ms.items()}},
-        "speedup_vs_full": round(fps / full_fps, 3),
+        "full_range": full,
+        "speedup_vs_full": round(fps / full["frames_per_s"], 3) if full else None,
         "stage_ms": {k: round(v, 5) for k, v in stage_avg.items()},
         "ms_per_step_with_events": round(dt_prof / args.steps * 1e3, 4),
         "bad_px_gt3": {"reduced_d": round(bad_d / max(nval, 1), 6), "reduced_dz": round(bad_z / max(nval, 1), 6),
-                       "full_range": round(full_bad / max(nval, 1), 6), "frames": "1-19"},
+                       "full_range": full["bad_px_gt3"] if full else None, "frames": "1-19"},
         "roofline": roofline,
     }
     if not args.no_cpu:

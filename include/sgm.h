@@ -148,8 +148,8 @@ int sgm_set_debug(sgm_context *ctx, int32_t on);
  * new accumulation, 0 stops it.  sgm_read_profile synchronises `stream`,
  * then writes the accumulated milliseconds of each stage (SGM_PROF_COUNT
  * doubles, in the order of the enum) and the number of frames measured. */
-enum { SGM_PROF_CENSUS = 0, SGM_PROF_PREDICT, SGM_PROF_COST, SGM_PROF_AGGREGATE, SGM_PROF_WTA,
-       SGM_PROF_COUNT };
+enum { SGM_PROF_CENSUS = 0, SGM_PROF_PREDICT, SGM_PROF_COST, SGM_PROF_AGG_H, SGM_PROF_AGG_V, SGM_PROF_WTA,
+       SGM_PROF_COUNT };   /* AGG_H: horizontal paths (timed on an internal stream); AGG_V: the others */
 int sgm_set_profiling(sgm_context *ctx, int32_t on);
 int sgm_read_profile(sgm_context *ctx, double *ms, int64_t *frames, void *stream);
 

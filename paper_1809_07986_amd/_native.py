@@ -22,7 +22,7 @@ EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", 
            "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_state", "sgm_set_state",
            "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
            "sgm_read_profile", "sgm_last_error")
-PROF_STAGES = ("census", "predict", "cost", "aggregate", "wta")
+PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta")
 
 
 class SgmParams(ctypes.Structure):

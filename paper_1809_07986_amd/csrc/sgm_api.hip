@@ -201,11 +201,33 @@ int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pi
         if (e != hipSuccess)
             return hip_fail(e, "cost launch");
     }
-    mk.begin(SGM_PROF_AGGREGATE);
-    e = launch_aggregate(g, b, mode == 0, s, ctx->side, ctx->fork, ctx->join);
-    mk.end(SGM_PROF_AGGREGATE);
+    // horizontal paths on the side stream, concurrently with the others
+    const bool fork = count_horizontal_paths(g) > 0;
+    if (fork) {
+        e = hipEventRecord(ctx->fork, s);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+        if (e != hipSuccess)
+            return hip_fail(e, "stream fork");
+        StageMark mh(ctx->prof, ctx->side);
+        mh.begin(SGM_PROF_AGG_H);
+        e = launch_agg_h(g, b, ctx->side);
+        mh.end(SGM_PROF_AGG_H);
+        if (e != hipSuccess)
+            return hip_fail(e, "horizontal aggregation launch");
+    }
+    mk.begin(SGM_PROF_AGG_V);
+    e = launch_agg_v(g, b, s);
+    mk.end(SGM_PROF_AGG_V);
     if (e != hipSuccess)
         return hip_fail(e, "aggregation launch");
+    if (fork) {
+        e = hipEventRecord(ctx->join, ctx->side);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, ctx->join, 0);
+        if (e != hipSuccess)
+            return hip_fail(e, "stream join");
+    }
     mk.begin(SGM_PROF_WTA);
     e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, s);
     mk.end(SGM_PROF_WTA);

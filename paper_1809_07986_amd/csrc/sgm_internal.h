@@ -65,12 +65,12 @@ hipError_t launch_given_windows(const Geometry &g, DevBuffers &b, const int32_t 
 hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const CorrectConst &cc,
                           hipStream_t s);
 hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
-// Eq. 1 aggregation of every enabled path.  Horizontal paths run on `side`
-// (forked from and joined back into `s` with the two events), the others on
-// `s`.  full_range: every window is [0, D-1] (one scanline per wave for the
-// horizontal paths).
-hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, bool full_range, hipStream_t s, hipStream_t side,
-                            hipEvent_t fork, hipEvent_t join);
+// Eq. 1 aggregation: horizontal paths (one scanline per wave) and the
+// vertical + diagonal paths (16 scanlines per block); the two launches are
+// independent and may run on different streams.
+int count_horizontal_paths(const Geometry &g);
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s);
 // mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
                               bool debug_sum, hipStream_t s);

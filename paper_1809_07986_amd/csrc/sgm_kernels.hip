@@ -989,11 +989,8 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
     }
 }
 
-hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, bool full_range, hipStream_t s, hipStream_t side,
-                            hipEvent_t fork, hipEvent_t join)
+static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv, int &nh, int &nv, int &maxv)
 {
-    (void)full_range;
-    AggArgs hv, vv;
     for (AggArgs *a : {&hv, &vv}) {
         a->cl = b.cen_l;
         a->cr = b.cen_r;
@@ -1008,8 +1005,7 @@ hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, bool full_range, h
         a->p1 = g.p1;
         a->p2 = g.p2;
     }
-    int nh = 0, nv = 0;
-    int maxv = 0;
+    nh = nv = maxv = 0;
     for (int k = 0; k < g.npaths; k++) {
         if (g.ry[k] == 0) {
             hv.rx[nh] = g.rx[k];
@@ -1026,44 +1022,50 @@ hipError_t launch_aggregate(const Geometry &g, DevBuffers &b, bool full_range, h
             nv++;
         }
     }
-    hipError_t e = hipSuccess;
-    if (nh) {
-        e = hipEventRecord(fork, s);
-        if (e == hipSuccess)
-            e = hipStreamWaitEvent(side, fork, 0);
-        if (e != hipSuccess)
-            return e;
-        size_t lds = agg_h_lds(g.W);
-        dim3 grd(g.H, nh);
-        if (g.D <= 64)
-            hipLaunchKernelGGL((k_agg_h<1>), grd, dim3(64), lds, side, hv);
-        else if (g.D <= 128)
-            hipLaunchKernelGGL((k_agg_h<2>), grd, dim3(64), lds, side, hv);
-        else
-            hipLaunchKernelGGL((k_agg_h<4>), grd, dim3(64), lds, side, hv);
-        e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    if (nv) {
-        size_t lds = agg_v_lds(g.D);
-        dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
-        if (g.D <= 64)
-            hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
-        else if (g.D <= 128)
-            hipLaunchKernelGGL((k_agg_v<8>), grd, dim3(AV_T), lds, s, vv);
-        else
-            hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
-        e = hipGetLastError();
-        if (e != hipSuccess)
-            return e;
-    }
-    if (nh) {
-        e = hipEventRecord(join, side);
-        if (e == hipSuccess)
-            e = hipStreamWaitEvent(s, join, 0);
-    }
-    return e;
+}
+
+int count_horizontal_paths(const Geometry &g)
+{
+    int n = 0;
+    for (int k = 0; k < g.npaths; k++)
+        n += g.ry[k] == 0;
+    return n;
+}
+
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s)
+{
+    AggArgs hv, vv;
+    int nh, nv, maxv;
+    agg_args(g, b, hv, vv, nh, nv, maxv);
+    if (!nh)
+        return hipSuccess;
+    size_t lds = agg_h_lds(g.W);
+    dim3 grd(g.H, nh);
+    if (g.D <= 64)
+        hipLaunchKernelGGL((k_agg_h<1>), grd, dim3(64), lds, s, hv);
+    else if (g.D <= 128)
+        hipLaunchKernelGGL((k_agg_h<2>), grd, dim3(64), lds, s, hv);
+    else
+        hipLaunchKernelGGL((k_agg_h<4>), grd, dim3(64), lds, s, hv);
+    return hipGetLastError();
+}
+
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s)
+{
+    AggArgs hv, vv;
+    int nh, nv, maxv;
+    agg_args(g, b, hv, vv, nh, nv, maxv);
+    if (!nv)
+        return hipSuccess;
+    size_t lds = agg_v_lds(g.D);
+    dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
+    if (g.D <= 64)
+        hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
+    else if (g.D <= 128)
+        hipLaunchKernelGGL((k_agg_v<8>), grd, dim3(AV_T), lds, s, vv);
+    else
+        hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
