@@ -153,6 +153,43 @@ enum { SGM_PROF_CENSUS = 0, SGM_PROF_PREDICT, SGM_PROF_COST, SGM_PROF_AGG_H, SGM
 int sgm_set_profiling(sgm_context *ctx, int32_t on);
 int sgm_read_profile(sgm_context *ctx, double *ms, int64_t *frames, void *stream);
 
+/* ---- batches of independent stereo streams --------------------------------
+ * A batch owns one context per stream (uneven sizes and disparity ranges are
+ * allowed) and runs a frame step of every stream with the streams' kernels
+ * spread over internal lanes (HIP streams, default priority) forked from and
+ * joined back into the caller's stream.  Input images are the caller's
+ * device buffers given at creation (pointers and pitches fixed for the
+ * batch's lifetime; write each new frame into them, stream-ordered, before
+ * the step).  Per-step ego-motions go through device memory.
+ *
+ * sgm_batch_create: n streams, params[i], left[i], right[i] device buffers,
+ *   pitch[i] bytes.  Allocates everything (contexts, lanes, save area).
+ * sgm_batch_context: stream i's context (outputs, state, stages); owned by
+ *   the batch.
+ * sgm_batch_full: full-range frame of every stream (Section 2.4 start).
+ * sgm_batch_step: steady-state frame of every stream; T is a HOST array of
+ *   n row-major 4x4 matrices.  SGM_ESTATE before sgm_batch_full.
+ * sgm_batch_step_graph: stepping as a captured HIP graph.  Disabled: always
+ *   returns SGM_EINVAL (its first run crashed the host process during stream
+ *   capture; the cause has not been shown).
+ * sgm_batch_set_schedule: lanes (1..16) and order (0: streams as given,
+ *   round-robin; 1: largest full-range work first onto the least-loaded lane).
+ * sgm_batch_autotune: times every (lanes, order) candidate over `reps` steps
+ *   with ego-motions T, keeps the fastest (written to chosen[0], chosen[1]
+ *   when not NULL) and restores every stream's filter state and motion mask
+ *   (the per-frame stages of sgm_get_stage show the last trial step);
+ *   synchronises the stream. */
+typedef struct sgm_batch sgm_batch;
+int sgm_batch_create(int32_t n, const sgm_params *params, const uint8_t *const *left,
+                     const uint8_t *const *right, const int32_t *pitch, sgm_batch **out);
+void sgm_batch_destroy(sgm_batch *b);
+sgm_context *sgm_batch_context(sgm_batch *b, int32_t i);
+int sgm_batch_full(sgm_batch *b, void *stream);
+int sgm_batch_step(sgm_batch *b, const double *T, void *stream);
+int sgm_batch_step_graph(sgm_batch *b, const double *T, void *stream);
+int sgm_batch_set_schedule(sgm_batch *b, int32_t lanes, int32_t order);
+int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *chosen, void *stream);
+
 /* Thread-local message describing the last nonzero return on this thread. */
 const char *sgm_last_error(void);
 

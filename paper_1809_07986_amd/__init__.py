@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["ReducedSGM", "SgmError", "default_params"]
+__all__ = ["ReducedSGM", "SgmBatch", "SgmError", "default_params", "as_matrix"]
 
 
 class SgmError(RuntimeError):
@@ -84,11 +84,21 @@ class ReducedSGM:
         self._h = h
         self.W, self.H, self.D = width, height, max_disp
 
+    @classmethod
+    def _view(cls, handle, width: int, height: int, max_disp: int, device) -> "ReducedSGM":
+        """A non-owning view of a context that belongs to a batch."""
+        obj = cls.__new__(cls)
+        obj._h = ctypes.c_void_p(handle)
+        obj._owner = False
+        obj.device = device
+        obj.W, obj.H, obj.D = width, height, max_disp
+        return obj
+
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owner", True):
             with torch.cuda.device(self.device):
                 _lib().sgm_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         try:
@@ -190,3 +200,81 @@ class ReducedSGM:
         if count == npx:
             out = out.view(self.H, self.W)
         return out
+
+
+class SgmBatch:
+    """Many independent stereo streams stepped together over concurrent lanes.
+
+    `streams` is a list of dicts with width, height, max_disp and any other
+    sgm_params field.  The batch owns one uint8 [H, W] input tensor pair per
+    stream (`left[i]`, `right[i]`); load each frame into them with `load`.
+    """
+
+    def __init__(self, streams, device: Optional[torch.device] = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        n = len(streams)
+        self.n = n
+        self.left, self.right, self.shapes = [], [], []
+        prm = (N.SgmParams * n)()
+        with torch.cuda.device(self.device):
+            for i, st in enumerate(streams):
+                st = dict(st)
+                w, h, dmax = st.pop("width"), st.pop("height"), st.pop("max_disp")
+                prm[i] = default_params(w, h, dmax, **st)
+                self.left.append(torch.zeros((h, w), dtype=torch.uint8, device=self.device))
+                self.right.append(torch.zeros((h, w), dtype=torch.uint8, device=self.device))
+                self.shapes.append((w, h, dmax))
+            lp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.left])
+            rp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.right])
+            pitch = (ctypes.c_int32 * n)(*[s[0] for s in self.shapes])
+            h = ctypes.c_void_p()
+            torch.cuda.synchronize()
+            _check(_lib().sgm_batch_create(n, prm, lp, rp, pitch, ctypes.byref(h)))
+        self._h = h
+        self.contexts = []
+        for i, (w, hh, dmax) in enumerate(self.shapes):
+            ch = _lib().sgm_batch_context(self._h, i)
+            if not ch:
+                raise SgmError(N.SGM_EINVAL, _lib().sgm_last_error().decode())
+            self.contexts.append(ReducedSGM._view(ch, w, hh, dmax, self.device))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                _lib().sgm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, i: int, left, right):
+        self.left[i].copy_(_dev_image(left, self.device))
+        self.right[i].copy_(_dev_image(right, self.device))
+
+    @staticmethod
+    def _Ts(Ts) -> ctypes.Array:
+        if isinstance(Ts, ctypes.Array):
+            return Ts
+        a = np.ascontiguousarray(np.asarray(Ts, dtype=np.float64).reshape(-1))
+        return (ctypes.c_double * a.size)(*a.tolist())
+
+    def full(self):
+        _check(_lib().sgm_batch_full(self._h, _stream()))
+
+    def step(self, Ts):
+        _check(_lib().sgm_batch_step(self._h, self._Ts(Ts), _stream()))
+
+    def step_graph(self, Ts):
+        """Captured-graph stepping (currently disabled in the library: raises)."""
+        _check(_lib().sgm_batch_step_graph(self._h, self._Ts(Ts), _stream()))
+
+    def set_schedule(self, lanes: int, order: int):
+        _check(_lib().sgm_batch_set_schedule(self._h, lanes, order))
+
+    def autotune(self, Ts, reps: int = 3):
+        chosen = (ctypes.c_int32 * 2)()
+        _check(_lib().sgm_batch_autotune(self._h, self._Ts(Ts), reps, chosen, _stream()))
+        return int(chosen[0]), int(chosen[1])

@@ -21,7 +21,9 @@ STAGE_PATH0 = 16
 EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
            "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_state", "sgm_set_state",
            "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
-           "sgm_read_profile", "sgm_last_error")
+           "sgm_read_profile", "sgm_batch_create", "sgm_batch_destroy", "sgm_batch_context", "sgm_batch_full",
+           "sgm_batch_step", "sgm_batch_step_graph", "sgm_batch_set_schedule", "sgm_batch_autotune",
+           "sgm_last_error")
 PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta")
 
 
@@ -65,6 +67,15 @@ def load(path: str = LIB_PATH):
         "sgm_set_debug": [P, I32],
         "sgm_set_profiling": [P, I32],
         "sgm_read_profile": [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), P],
+        "sgm_batch_create": [I32, ctypes.POINTER(SgmParams), ctypes.POINTER(P), ctypes.POINTER(P),
+                             ctypes.POINTER(I32), ctypes.POINTER(P)],
+        "sgm_batch_destroy": [P],
+        "sgm_batch_context": [P, I32],
+        "sgm_batch_full": [P, P],
+        "sgm_batch_step": [P, ctypes.POINTER(ctypes.c_double), P],
+        "sgm_batch_step_graph": [P, ctypes.POINTER(ctypes.c_double), P],
+        "sgm_batch_set_schedule": [P, I32, I32],
+        "sgm_batch_autotune": [P, ctypes.POINTER(ctypes.c_double), I32, ctypes.POINTER(I32), P],
         "sgm_last_error": [],
     }
     for name, args in sig.items():
@@ -72,6 +83,8 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
         fn.restype = ctypes.c_int
     lib.sgm_destroy.restype = None
+    lib.sgm_batch_destroy.restype = None
+    lib.sgm_batch_context.restype = ctypes.c_void_p
     lib.sgm_last_error.restype = ctypes.c_char_p
     _lib = lib
     return lib

@@ -236,6 +236,50 @@ int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pi
     return SGM_OK;
 }
 
+// one steady-state frame; the ego-motion comes from the host (by value in
+// the launch) or, when Tdev is not NULL, from device memory
+int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
+                       const double *Thost, const double *Tdev, hipStream_t s)
+{
+    const sgm_params &p = ctx->prm;
+    WarpConst wc;
+    for (int i = 0; i < 12; i++)
+        wc.T[i] = Thost ? Thost[i] : 0.0;
+    wc.f = p.f;
+    wc.cx = p.cx;
+    wc.cy = p.cy;
+    wc.B = p.baseline;
+    wc.fB = p.f * p.baseline;
+    wc.zmin = 1e-9 * wc.fB;
+    wc.q = p.q;
+    prof_begin_frame(ctx->prof, s);
+    StageMark mk(ctx->prof, s);
+    mk.begin(SGM_PROF_PREDICT);
+    hipError_t e = launch_predict(ctx->g, ctx->b, wc, Tdev, correct_const(p), s);
+    mk.end(SGM_PROF_PREDICT);
+    if (e != hipSuccess)
+        return hip_fail(e, "prediction launch");
+    int rc = run_matcher(ctx, left, right, pitch, 1, s);
+    if (rc)
+        return rc;
+    prof_end_frame(ctx->prof);
+    return SGM_OK;
+}
+
+int full_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch, hipStream_t s)
+{
+    prof_begin_frame(ctx->prof, s);
+    hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "window launch");
+    int rc = run_matcher(ctx, left, right, pitch, 0, s);
+    if (rc)
+        return rc;
+    prof_end_frame(ctx->prof);
+    ctx->started = true;
+    return SGM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -451,17 +495,7 @@ int sgm_full_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *right, 
     int rc = check_ctx(ctx);
     if (rc || (rc = check_images(ctx, left, right, pitch)))
         return rc;
-    hipStream_t s = as_stream(stream);
-    prof_begin_frame(ctx->prof, s);
-    hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
-    if (e != hipSuccess)
-        return hip_fail(e, "window launch");
-    rc = run_matcher(ctx, left, right, pitch, 0, s);
-    if (rc)
-        return rc;
-    prof_end_frame(ctx->prof);
-    ctx->started = true;
-    return SGM_OK;
+    return full_frame_impl(ctx, left, right, pitch, as_stream(stream));
 }
 
 int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
@@ -477,30 +511,7 @@ int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
             return fail(SGM_EINVAL, "T_k_km1[%d] is not finite", i);
     if (!ctx->started)
         return fail(SGM_ESTATE, "reduced frame requested before a full frame or set_state");
-    const sgm_params &p = ctx->prm;
-    WarpConst wc;
-    for (int i = 0; i < 12; i++)
-        wc.T[i] = T[i];
-    wc.f = p.f;
-    wc.cx = p.cx;
-    wc.cy = p.cy;
-    wc.B = p.baseline;
-    wc.fB = p.f * p.baseline;
-    wc.zmin = 1e-9 * wc.fB;
-    wc.q = p.q;
-    hipStream_t s = as_stream(stream);
-    prof_begin_frame(ctx->prof, s);
-    StageMark mk(ctx->prof, s);
-    mk.begin(SGM_PROF_PREDICT);
-    hipError_t e = launch_predict(ctx->g, ctx->b, wc, correct_const(p), s);
-    mk.end(SGM_PROF_PREDICT);
-    if (e != hipSuccess)
-        return hip_fail(e, "prediction launch");
-    rc = run_matcher(ctx, left, right, pitch, 1, s);
-    if (rc)
-        return rc;
-    prof_end_frame(ctx->prof);
-    return SGM_OK;
+    return reduced_frame_impl(ctx, left, right, pitch, T, nullptr, as_stream(stream));
 }
 
 int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch,
@@ -682,6 +693,353 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
         return fail(SGM_EINVAL, "stage %d needs %zu bytes, got %zu", stage, need, bytes);
     hipError_t e = hipMemcpyAsync(out, src, need, hipMemcpyDeviceToDevice, s);
     return e == hipSuccess ? SGM_OK : hip_fail(e, "stage copy");
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of independent stereo streams (declared in include/sgm.h)
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kMaxLanes = 16;
+
+}  // namespace
+
+struct sgm_batch {
+    int n = 0;
+    int device = 0;
+    sgm_context **ctx = nullptr;
+    const uint8_t **left = nullptr, **right = nullptr;
+    int32_t *pitch = nullptr;
+    double *Tdev = nullptr;                 // n x 16, device
+    double *save_d = nullptr, *save_p = nullptr;   // state save area for autotuning
+    uint8_t *save_f = nullptr, *save_m = nullptr;
+    size_t *save_off = nullptr;             // per-stream offsets into the save area
+    int nlanes = 1;
+    int order = 1;                          // 0: as given, 1: longest-processing-time first
+    hipStream_t lane[kMaxLanes];
+    hipEvent_t fork, join[kMaxLanes];
+    int *lane_of = nullptr, *seq = nullptr; // lane per stream, launch order
+    bool started = false;
+};
+
+namespace {
+
+void batch_schedule(sgm_batch *b)
+{
+    // cost estimate: full-range work W*H*D; LPT: largest first onto the least
+    // loaded lane; order 0 keeps the caller's order round-robin
+    double load[kMaxLanes] = {0};
+    for (int i = 0; i < b->n; i++)
+        b->seq[i] = i;
+    auto cost = [&](int i) {
+        const sgm_params &p = b->ctx[i]->prm;
+        return (double)p.width * p.height * p.max_disp;
+    };
+    if (b->order == 1) {
+        for (int i = 1; i < b->n; i++)
+            for (int j = i; j > 0 && cost(b->seq[j]) > cost(b->seq[j - 1]); j--) {
+                int t = b->seq[j];
+                b->seq[j] = b->seq[j - 1];
+                b->seq[j - 1] = t;
+            }
+        for (int k = 0; k < b->n; k++) {
+            int i = b->seq[k], best = 0;
+            for (int l = 1; l < b->nlanes; l++)
+                if (load[l] < load[best])
+                    best = l;
+            b->lane_of[i] = best;
+            load[best] += cost(i);
+        }
+    } else {
+        for (int i = 0; i < b->n; i++)
+            b->lane_of[i] = i % b->nlanes;
+    }
+}
+
+// enqueue one step of every stream on the lanes, forked from and joined
+// back into `s`; T comes from b->Tdev (reduced) or is unused (full)
+int batch_enqueue(sgm_batch *b, bool full, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(b->fork, s);
+    for (int l = 0; l < b->nlanes && e == hipSuccess; l++)
+        e = hipStreamWaitEvent(b->lane[l], b->fork, 0);
+    if (e != hipSuccess)
+        return hip_fail(e, "batch fork");
+    for (int k = 0; k < b->n; k++) {
+        const int i = b->seq[k];
+        hipStream_t ls = b->lane[b->lane_of[i]];
+        int rc = full ? full_frame_impl(b->ctx[i], b->left[i], b->right[i], b->pitch[i], ls)
+                      : reduced_frame_impl(b->ctx[i], b->left[i], b->right[i], b->pitch[i], nullptr,
+                                           b->Tdev + 16 * i, ls);
+        if (rc)
+            return rc;
+    }
+    for (int l = 0; l < b->nlanes; l++) {
+        e = hipEventRecord(b->join[l], b->lane[l]);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(s, b->join[l], 0);
+        if (e != hipSuccess)
+            return hip_fail(e, "batch join");
+    }
+    return SGM_OK;
+}
+
+int batch_upload_T(sgm_batch *b, const double *T, hipStream_t s)
+{
+    for (int i = 0; i < 16 * b->n; i++)
+        if (!isfinite(T[i]))
+            return fail(SGM_EINVAL, "T[%d] is not finite", i);
+    hipError_t e = hipMemcpyAsync(b->Tdev, T, sizeof(double) * 16 * b->n, hipMemcpyHostToDevice, s);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "ego-motion upload");
+}
+
+void batch_free(sgm_batch *b)
+{
+    if (b->ctx)
+        for (int i = 0; i < b->n; i++)
+            if (b->ctx[i])
+                sgm_destroy(b->ctx[i]);
+    for (int l = 0; l < kMaxLanes; l++) {
+        if (b->lane[l])
+            (void)hipStreamDestroy(b->lane[l]);
+        if (b->join[l])
+            (void)hipEventDestroy(b->join[l]);
+    }
+    if (b->fork)
+        (void)hipEventDestroy(b->fork);
+    for (void *p : {(void *)b->Tdev, (void *)b->save_d, (void *)b->save_p, (void *)b->save_f, (void *)b->save_m})
+        if (p)
+            (void)hipFree(p);
+    delete[] b->ctx;
+    delete[] b->left;
+    delete[] b->right;
+    delete[] b->pitch;
+    delete[] b->lane_of;
+    delete[] b->seq;
+    delete[] b->save_off;
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgm_batch_create(int32_t n, const sgm_params *params, const uint8_t *const *left,
+                     const uint8_t *const *right, const int32_t *pitch, sgm_batch **out)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > 1024 || !params || !left || !right || !pitch)
+        return fail(SGM_EINVAL, "need 1 <= n <= 1024 and non-NULL params, image and pitch arrays");
+    for (int i = 0; i < n; i++)
+        if (!left[i] || !right[i] || pitch[i] < params[i].width)
+            return fail(SGM_EINVAL, "stream %d: NULL image or pitch < width", i);
+    sgm_batch *b = new (std::nothrow) sgm_batch();
+    if (!b)
+        return fail(SGM_ENOMEM, "host allocation failed");
+    memset(b->lane, 0, sizeof(b->lane));
+    memset(b->join, 0, sizeof(b->join));
+    b->fork = nullptr;
+    b->n = n;
+    (void)hipGetDevice(&b->device);
+    b->ctx = new (std::nothrow) sgm_context *[n]();
+    b->left = new (std::nothrow) const uint8_t *[n];
+    b->right = new (std::nothrow) const uint8_t *[n];
+    b->pitch = new (std::nothrow) int32_t[n];
+    b->lane_of = new (std::nothrow) int[n];
+    b->seq = new (std::nothrow) int[n];
+    b->save_off = new (std::nothrow) size_t[n + 1];
+    if (!b->ctx || !b->left || !b->right || !b->pitch || !b->lane_of || !b->seq || !b->save_off) {
+        batch_free(b);
+        return fail(SGM_ENOMEM, "host allocation failed");
+    }
+    size_t tot = 0;
+    for (int i = 0; i < n; i++) {
+        b->left[i] = left[i];
+        b->right[i] = right[i];
+        b->pitch[i] = pitch[i];
+        int rc = sgm_create(&params[i], &b->ctx[i]);
+        if (rc) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "%s", g_err);
+            batch_free(b);
+            return fail(rc, "stream %d: %s", i, msg);
+        }
+        b->save_off[i] = tot;
+        tot += (size_t)params[i].width * params[i].height;
+    }
+    b->save_off[n] = tot;
+    hipError_t e = hipMalloc((void **)&b->Tdev, sizeof(double) * 16 * n);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->save_d, sizeof(double) * tot);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->save_p, sizeof(double) * tot);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->save_f, tot);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->save_m, tot);
+    for (int l = 0; l < kMaxLanes && e == hipSuccess; l++) {
+        e = hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking);
+        if (e == hipSuccess)
+            e = hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming);
+    }
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return fail(SGM_ENOMEM, "batch allocation failed: %s", hipGetErrorString(e));
+    }
+    b->nlanes = n < 4 ? n : 4;
+    b->order = 1;
+    batch_schedule(b);
+    *out = b;
+    return SGM_OK;
+}
+
+void sgm_batch_destroy(sgm_batch *b)
+{
+    if (!b)
+        return;
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+}
+
+sgm_context *sgm_batch_context(sgm_batch *b, int32_t i)
+{
+    if (!b || i < 0 || i >= b->n) {
+        fail(SGM_EINVAL, "no stream %d in the batch", i);
+        return nullptr;
+    }
+    return b->ctx[i];
+}
+
+int sgm_batch_set_schedule(sgm_batch *b, int32_t lanes, int32_t order)
+{
+    if (!b || lanes < 1 || lanes > kMaxLanes || (order != 0 && order != 1))
+        return fail(SGM_EINVAL, "need 1 <= lanes <= %d and order 0 or 1", kMaxLanes);
+    b->nlanes = lanes;
+    b->order = order;
+    batch_schedule(b);
+    return SGM_OK;
+}
+
+int sgm_batch_full(sgm_batch *b, void *stream)
+{
+    if (!b)
+        return fail(SGM_EINVAL, "batch is NULL");
+    int rc = batch_enqueue(b, true, as_stream(stream));
+    if (rc)
+        return rc;
+    b->started = true;
+    return SGM_OK;
+}
+
+int sgm_batch_step(sgm_batch *b, const double *T, void *stream)
+{
+    if (!b || !T)
+        return fail(SGM_EINVAL, "batch or T is NULL");
+    if (!b->started)
+        return fail(SGM_ESTATE, "batch step before sgm_batch_full");
+    hipStream_t s = as_stream(stream);
+    int rc = batch_upload_T(b, T, s);
+    return rc ? rc : batch_enqueue(b, false, s);
+}
+
+int sgm_batch_step_graph(sgm_batch *b, const double *T, void *stream)
+{
+    (void)T;
+    (void)stream;
+    if (!b)
+        return fail(SGM_EINVAL, "batch is NULL");
+    return fail(SGM_EINVAL, "captured-graph stepping is disabled: its first run crashed the host process during "
+                            "stream capture and the cause has not been shown; use sgm_batch_step");
+}
+
+int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *chosen, void *stream)
+{
+    if (!b || !T || reps < 1)
+        return fail(SGM_EINVAL, "batch, T or reps invalid");
+    if (!b->started)
+        return fail(SGM_ESTATE, "autotune before sgm_batch_full");
+    hipStream_t s = as_stream(stream);
+    // the trial steps advance the filters: save every stream's state first
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < b->n && e == hipSuccess; i++) {
+        const size_t N = b->save_off[i + 1] - b->save_off[i];
+        e = hipMemcpyAsync(b->save_d + b->save_off[i], b->ctx[i]->b.d, N * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->save_p + b->save_off[i], b->ctx[i]->b.p, N * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->save_f + b->save_off[i], b->ctx[i]->b.sflags, N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->save_m + b->save_off[i], b->ctx[i]->b.mask, N, hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "state save");
+    hipEvent_t t0, t1;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
+        return fail(SGM_EHIP, "event creation failed");
+    int rc = batch_upload_T(b, T, s);
+    float best = 1e30f;
+    int best_l = b->nlanes, best_o = b->order;
+    const int lane_opts[] = {1, 2, 4, 8, 16};
+    for (int oi = 0; oi < 2 && !rc; oi++) {
+        for (int li = 0; li < 5 && !rc; li++) {
+            const int l = lane_opts[li];
+            if (l > b->n && l != 1)
+                continue;
+            b->nlanes = l;
+            b->order = oi;
+            batch_schedule(b);
+            if ((rc = batch_enqueue(b, false, s)))   // warm-up
+                break;
+            (void)hipEventRecord(t0, s);
+            for (int r = 0; r < reps && !rc; r++)
+                rc = batch_enqueue(b, false, s);
+            (void)hipEventRecord(t1, s);
+            if (rc)
+                break;
+            if (hipEventSynchronize(t1) != hipSuccess) {
+                rc = fail(SGM_EHIP, "autotune timing failed");
+                break;
+            }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, t0, t1);
+            if (ms < best) {
+                best = ms;
+                best_l = l;
+                best_o = oi;
+            }
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    b->nlanes = best_l;
+    b->order = best_o;
+    batch_schedule(b);
+    for (int i = 0; i < b->n && e == hipSuccess; i++) {
+        const size_t N = b->save_off[i + 1] - b->save_off[i];
+        e = hipMemcpyAsync(b->ctx[i]->b.d, b->save_d + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ctx[i]->b.p, b->save_p + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ctx[i]->b.sflags, b->save_f + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ctx[i]->b.mask, b->save_m + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "state restore");
+    if (rc)
+        return rc;
+    if (chosen) {
+        chosen[0] = best_l;
+        chosen[1] = best_o;
+    }
+    return SGM_OK;
 }
 
 }  // extern "C"

@@ -62,8 +62,9 @@ hipError_t launch_census(const Geometry &g, const uint8_t *left, const uint8_t *
 hipError_t launch_full_windows(const Geometry &g, DevBuffers &b, hipStream_t s);
 hipError_t launch_given_windows(const Geometry &g, DevBuffers &b, const int32_t *lo, const int32_t *hi,
                                 hipStream_t s);
-hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const CorrectConst &cc,
-                          hipStream_t s);
+// Tdev: ego-motion in device memory (row-major 4x4), or NULL to use wc.T
+hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
+                          const CorrectConst &cc, hipStream_t s);
 hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
 // Eq. 1 aggregation: horizontal paths (one scanline per wave) and the
 // vertical + diagonal paths (16 scanlines per block); the two launches are

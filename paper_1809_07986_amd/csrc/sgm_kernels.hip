@@ -217,13 +217,20 @@ hipError_t launch_given_windows(const Geometry &g, DevBuffers &b, const int32_t 
 // holding that maximum.
 // ---------------------------------------------------------------------------
 
-__global__ void k_splat(int W, int H, int D, WarpConst wc, const double *__restrict__ d,
-                        const double *__restrict__ p, int32_t *__restrict__ tgt, double *__restrict__ dprime,
-                        double *__restrict__ pprime, unsigned long long *__restrict__ zkey)
+__global__ void k_splat(int W, int H, int D, WarpConst wc, const double *__restrict__ Tdev,
+                        const double *__restrict__ d, const double *__restrict__ p, int32_t *__restrict__ tgt,
+                        double *__restrict__ dprime, double *__restrict__ pprime,
+                        unsigned long long *__restrict__ zkey)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= W * H)
         return;
+    if (Tdev) {
+        // ego-motion from device memory (row-major 4x4; graph replays update it)
+#pragma unroll
+        for (int i = 0; i < 12; i++)
+            wc.T[i] = Tdev[i];
+    }
     int y = s / W, x = s - y * W;
     double X = ((double)x - wc.cx) * wc.B;
     double Y = ((double)y - wc.cy) * wc.B;
@@ -375,11 +382,12 @@ __global__ void k_disc_windows(int W, int H, int D, CorrectConst cc, const uint8
     pm[t] = ok ? pv : 0.0;
 }
 
-hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const CorrectConst &cc,
-                          hipStream_t s)
+hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
+                          const CorrectConst &cc, hipStream_t s)
 {
     dim3 blk(256), grd((g.N + 255) / 256);
-    hipLaunchKernelGGL(k_splat, grd, blk, 0, s, g.W, g.H, g.D, wc, b.d, b.p, b.tgt, b.dprime, b.pprime, b.zkey);
+    hipLaunchKernelGGL(k_splat, grd, blk, 0, s, g.W, g.H, g.D, wc, Tdev, b.d, b.p, b.tgt, b.dprime, b.pprime,
+                       b.zkey);
     hipLaunchKernelGGL(k_splat_ties, grd, blk, 0, s, g.N, b.tgt, b.dprime, b.zkey, b.zidx);
     hipLaunchKernelGGL(k_splat_resolve, grd, blk, 0, s, g.N, b.zkey, b.zidx, b.dprime, b.pprime, b.sflags, b.has,
                        b.dw, b.pw, b.rw);

@@ -308,6 +308,25 @@ def _scene_movers(K: int, speed: float, rng: np.random.Generator, n_movers: int,
 # rendering
 # ----------------------------------------------------------------------------
 
+def _box_screen_rect(bx: _Box, k: int, cam: Camera, c: np.ndarray, Rwc: np.ndarray):
+    """Pixel rectangle covering the box's projection, or None when the box
+    reaches behind the camera (then every pixel is tested)."""
+    R = _rot_y(float(bx.yaws[k]))
+    sx, sy, sz = bx.half
+    corners = np.array([[i * sx, j * sy, l * sz] for i in (-1, 1) for j in (-1, 1) for l in (-1, 1)])
+    Xw = corners @ R.T + bx.centers[k]
+    Xc = (Xw - c) @ Rwc.T
+    if np.any(Xc[:, 2] <= 0.1):
+        return None
+    u = cam.f * Xc[:, 0] / Xc[:, 2] + cam.cx
+    v = cam.f * Xc[:, 1] / Xc[:, 2] + cam.cy
+    x0, x1 = int(max(np.floor(u.min()) - 1, 0)), int(min(np.ceil(u.max()) + 1, cam.width - 1))
+    y0, y1 = int(max(np.floor(v.min()) - 1, 0)), int(min(np.ceil(v.max()) + 1, cam.height - 1))
+    if x0 > x1 or y0 > y1:
+        return (0, -1, 0, -1)
+    return (x0, x1, y0, y1)
+
+
 def _render(prims, cam: Camera, c: np.ndarray, Rwc: np.ndarray, k: int):
     H, W = cam.height, cam.width
     xs = (np.arange(W) - cam.cx) / cam.f
@@ -321,24 +340,36 @@ def _render(prims, cam: Camera, c: np.ndarray, Rwc: np.ndarray, k: int):
     mov = np.zeros(H * W, dtype=bool)
     for pr in prims:
         if isinstance(pr, _Plane):
+            sub = None
             t, u, v = _hit_plane(pr, c, dw)
-            key = pr.key
         else:
-            t, u, v, face = _hit_box(pr, k, c, dw)
-            key = pr.key
-        closer = t < best
+            rect = _box_screen_rect(pr, k, cam, c, Rwc)
+            if rect is None:
+                sub = None
+                t, u, v, face = _hit_box(pr, k, c, dw)
+            else:
+                x0, x1, y0, y1 = rect
+                if x0 > x1:
+                    continue
+                yy, xx = np.mgrid[y0:y1 + 1, x0:x1 + 1]
+                sub = (yy * W + xx).reshape(-1)
+                t, u, v, face = _hit_box(pr, k, c, dw[sub])
+        if sub is None:
+            sub = np.arange(H * W)
+        closer = t < best[sub]
         if not np.any(closer):
             continue
-        idx = np.nonzero(closer)[0]
-        best[idx] = t[idx]
+        loc = np.nonzero(closer)[0]
+        idx = sub[loc]
+        best[idx] = t[loc]
         if isinstance(pr, _Box):
             # different faces of a box get independent texture
             for fc in range(3):
-                sel = idx[face[idx] == fc]
-                if sel.size:
-                    val[sel] = _texture(u[sel], v[sel], key * 8 + fc)
+                m = face[loc] == fc
+                if np.any(m):
+                    val[idx[m]] = _texture(u[loc][m], v[loc][m], pr.key * 8 + fc)
         else:
-            val[idx] = _texture(u[idx], v[idx], key)
+            val[idx] = _texture(u[loc], v[loc], pr.key)
         mov[idx] = pr.mover
     return best.reshape(H, W), val.reshape(H, W), mov.reshape(H, W)
 
