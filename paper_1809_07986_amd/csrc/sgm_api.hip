@@ -332,6 +332,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     g.H = prm->height;
     g.D = prm->max_disp;
     g.N = g.W * g.H;
+    g.lr_stride = (((size_t)g.N * g.D) + 255) & ~(size_t)255;
     g.cw = prm->census_w;
     g.ch = prm->census_h;
     g.nbits = g.cw * g.ch - 1;
@@ -358,7 +359,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.off, N + 1));
     A(dalloc(&b.scan_part, 4200));
     A(dalloc(&b.cost, cells));
-    A(dalloc(&b.lr, cells * g.npaths));
+    A(dalloc(&b.lr, g.lr_stride * g.npaths));
     A(dalloc(&b.sum, cells));
     A(dalloc(&b.d, N));
     A(dalloc(&b.p, N));
@@ -683,7 +684,7 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
                 }
             if (idx < 0)
                 return fail(SGM_EINVAL, "path %d is not enabled", k);
-            src = b.lr + (size_t)idx * N * g.D;
+            src = b.lr + (size_t)idx * g.lr_stride;
             need = M;
             break;
         }

@@ -41,6 +41,7 @@ struct DevBuffers {
 
 struct Geometry {
     int W, H, D, N;
+    size_t lr_stride;          // bytes between the path-loss buffers: N*D rounded up to 256
     int cw, ch, nbits;
     int p1, p2;
     int npaths;

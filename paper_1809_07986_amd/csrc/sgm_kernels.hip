@@ -1005,7 +1005,7 @@ static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv,
         a->win = b.win;
         a->off = b.off;
         a->lr = b.lr;
-        a->lr_stride = (size_t)g.N * g.D;
+        a->lr_stride = g.lr_stride;
         a->W = g.W;
         a->H = g.H;
         a->D = g.D;
@@ -1099,7 +1099,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        double *__restrict__ d_state, double *__restrict__ p_state,
                                                        uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags)
 {
-    __shared__ uint16_t ssum[WTA_NG][kMaxDisp];
+    __shared__ uint16_t ssum[WTA_NG][kMaxDisp + 8];
     const int grp = threadIdx.x / WTA_G, lane = threadIdx.x % WTA_G;
     const int t = blockIdx.x * WTA_NG + grp;
     if (t >= N)
@@ -1107,15 +1107,33 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     const uint32_t o = off[t];
     const uint32_t wv = win[t];
     const int lo = (int)(wv & 255), w = (int)(wv >> 8) + 1, hi = lo + w - 1;
+    // each lane sums four consecutive cells of every path from aligned
+    // dwords (16-bit halves: even and odd bytes; S <= 8 * 148 < 2^16).
+    // Cells before o or past o+w-1 in the dwords belong to other pixels
+    // and are ignored.
+    const uint32_t a0 = o & ~3u;              // first aligned dword of the window
+    const int lead = (int)(o - a0);           // cells of the previous pixel in it
+    const int ndw = (lead + w + 3) >> 2;
     uint32_t key = 0x7FFFFFFFu;   // above every real key (S << 9 | slot < 2^20)
-    for (int sl = lane; sl < w; sl += WTA_G) {
-        uint32_t sv = 0;
-        for (int k = 0; k < npaths; k++)
-            sv += lr[(size_t)k * lr_stride + o + sl];
-        ssum[grp][sl] = (uint16_t)sv;
-        if (dbg_sum)
-            dbg_sum[o + sl] = (uint16_t)sv;
-        key = min(key, (sv << 9) | (uint32_t)sl);
+    for (int q = lane; q < ndw; q += WTA_G) {
+        const uint32_t byte0 = a0 + 4u * (uint32_t)q;
+        uint32_t ev = 0, od = 0;
+        for (int k = 0; k < npaths; k++) {
+            const uint32_t v = *(const uint32_t *)(lr + (size_t)k * lr_stride + byte0);
+            ev += v & 0x00FF00FFu;
+            od += (v >> 8) & 0x00FF00FFu;
+        }
+        const uint32_t s4[4] = {ev & 0xFFFFu, od & 0xFFFFu, ev >> 16, od >> 16};
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            const int sl = 4 * q + b - lead;      // slot within the window
+            if (sl >= 0 && sl < w) {
+                ssum[grp][sl] = (uint16_t)s4[b];
+                if (dbg_sum)
+                    dbg_sum[o + sl] = (uint16_t)s4[b];
+                key = min(key, (s4[b] << 9) | (uint32_t)sl);
+            }
+        }
     }
     key = (uint32_t)row_min16((int)key);   // keys < 2^31: the signed min is the unsigned min
     wave_lds_sync();
@@ -1160,7 +1178,7 @@ hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectCon
                               bool debug_sum, hipStream_t s)
 {
     hipLaunchKernelGGL(k_wta_correct, dim3((g.N + WTA_NG - 1) / WTA_NG), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
-                       mode, b.lr, (size_t)g.N * g.D, b.win, b.off, b.flags, b.dhat, b.pm,
+                       mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags);
     return hipGetLastError();
 }
