@@ -120,7 +120,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--full-steps", type=int, default=100)
-    ap.add_argument("--cpu-frames", type=int, default=4)
+    ap.add_argument("--cpu-frames", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-full", action="store_true", help="skip the full-range comparison (profiling runs)")
     ap.add_argument("--workload", choices=("driving", "batched"), default="driving",
