@@ -20,10 +20,11 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "correct",
-           "OracleFilter", "PRED", "RESET", "FULLWIN", "PATH_DX", "PATH_DY"]
+__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux",
+           "learned_windows", "correct", "correct_ex", "OracleFilter", "PRED", "RESET", "FULLWIN", "GATEFAIL",
+           "PATH_DX", "PATH_DY"]
 
-PRED, RESET, FULLWIN = 1, 2, 4
+PRED, RESET, FULLWIN, GATEFAIL = 1, 2, 4, 8
 # path k has direction r = (PATH_DX[k], PATH_DY[k]); the predecessor of p is p - r
 PATH_DX = (+1, -1, 0, 0, +1, -1, -1, +1)
 PATH_DY = (0, 0, +1, -1, +1, -1, +1, -1)
@@ -110,8 +111,12 @@ def _load():
             lib.orc_correct.argtypes = [P, P, P, P, P, P, P, P, P, P, P, P]
             lib.orc_full_frame.argtypes = [P, P, P, P, P, P, P, P, P, P, P]
             lib.orc_reduced_frame.argtypes = [P] + [P] * 14
+            lib.orc_predict_aux.argtypes = [P] * 12
+            lib.orc_learned_windows.argtypes = [P] * 6
+            lib.orc_correct_ex.argtypes = [P] * 14
             for name in ("orc_census", "orc_cost", "orc_aggregate", "orc_wta", "orc_match", "orc_predict",
-                         "orc_correct", "orc_full_frame", "orc_reduced_frame"):
+                         "orc_correct", "orc_full_frame", "orc_reduced_frame", "orc_predict_aux",
+                         "orc_learned_windows", "orc_correct_ex"):
                 getattr(lib, name).restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -204,6 +209,61 @@ def predict(prm: Params, d: np.ndarray, p: np.ndarray, sflags: np.ndarray, T: np
     return dhat, pm, flags, lo, hi
 
 
+def predict_aux(prm: Params, d, p, sflags, T, aux):
+    """predict() that also carries a per-source value with the warp winner
+    -> (dhat, pm, flags, lo, hi, aux_out); aux_out is 0 for filled holes and
+    pixels without prediction."""
+    d, p = _c(d, np.float64), _c(p, np.float64)
+    sflags = _c(sflags, np.uint8)
+    aux = _c(aux, np.float64)
+    T = _c(T, np.float64).reshape(16)
+    H, W = d.shape
+    dhat = np.zeros((H, W), np.float64)
+    pm = np.zeros((H, W), np.float64)
+    flags = np.zeros((H, W), np.uint8)
+    lo = np.zeros((H, W), np.int32)
+    hi = np.zeros((H, W), np.int32)
+    aux_out = np.zeros((H, W), np.float64)
+    cp = prm.c()
+    _check(_load().orc_predict_aux(ctypes.byref(cp), _p(d), _p(p), _p(sflags), _p(aux), _p(T), _p(dhat),
+                                   _p(pm), _p(flags), _p(lo), _p(hi), _p(aux_out)), "predict_aux")
+    return dhat, pm, flags, lo, hi, aux_out
+
+
+def learned_windows(prm: Params, dhat, hw, flags, lo, hi):
+    """Windows [floor(dhat - hw), ceil(dhat + hw)] for pixels not already at
+    the full range; hw >= 32 sends a pixel to the full range.  Returns new
+    (flags, lo, hi)."""
+    dhat, hw = _c(dhat, np.float64), _c(hw, np.float64)
+    flags = np.array(flags, np.uint8, copy=True, order="C")
+    lo = np.array(lo, np.int32, copy=True, order="C")
+    hi = np.array(hi, np.int32, copy=True, order="C")
+    cp = prm.c()
+    _check(_load().orc_learned_windows(ctypes.byref(cp), _p(dhat), _p(hw), _p(flags), _p(lo), _p(hi)),
+           "learned_windows")
+    return flags, lo, hi
+
+
+def correct_ex(prm: Params, dhat, pm, flags, lo, hi, dstar, dz, rpix=None):
+    """correct() with an optional per-pixel measurement variance; GATEFAIL
+    pixels restart from the measurement and stay marked moving.
+    -> (d, p, mask, sflags, nu)."""
+    dhat, pm, dz = _c(dhat, np.float64), _c(pm, np.float64), _c(dz, np.float64)
+    flags = _c(flags, np.uint8)
+    lo, hi, dstar = _c(lo, np.int32), _c(hi, np.int32), _c(dstar, np.int32)
+    rp = None if rpix is None else _c(rpix, np.float64)
+    H, W = dhat.shape
+    d = np.zeros((H, W), np.float64)
+    p = np.zeros((H, W), np.float64)
+    mask = np.zeros((H, W), np.uint8)
+    sflags = np.zeros((H, W), np.uint8)
+    nu = np.zeros((H, W), np.float64)
+    cp = prm.c()
+    _check(_load().orc_correct_ex(ctypes.byref(cp), _p(dhat), _p(pm), _p(flags), _p(lo), _p(hi), _p(dstar),
+                                  _p(dz), _p(rp), _p(d), _p(p), _p(mask), _p(sflags), _p(nu)), "correct_ex")
+    return d, p, mask, sflags, nu
+
+
 def correct(prm: Params, dhat, pm, flags, lo, hi, dstar, dz):
     """Kalman correction + innovation test -> (d, p, mask, sflags)."""
     dhat, pm, dz = _c(dhat, np.float64), _c(pm, np.float64), _c(dz, np.float64)
@@ -242,6 +302,10 @@ class OracleFilter:
         self.dhat = np.zeros((H, W), np.float64)
         self.pm = np.zeros((H, W), np.float64)
         self.flags = np.zeros((H, W), np.uint8)
+        self.nu = np.zeros((H, W), np.float64)      # innovation of the last frame
+        self.nu_w = np.zeros((H, W), np.float64)    # previous innovation carried by the warp
+        self.hw = None
+        self.rpix = None
         self.started = False
 
     def full_frame(self, left, right):
@@ -251,6 +315,7 @@ class OracleFilter:
                                       _p(self.sflags), _p(self.mask), _p(self.lo), _p(self.hi),
                                       _p(self.dstar), _p(self.dz)), "full_frame")
         self.flags[:] = FULLWIN
+        self.nu[:] = 0.0
         self.started = True
 
     def reduced_frame(self, left, right, T):
@@ -263,6 +328,49 @@ class OracleFilter:
                                          _p(self.p), _p(self.sflags), _p(self.mask), _p(self.dhat),
                                          _p(self.pm), _p(self.flags), _p(self.lo), _p(self.hi),
                                          _p(self.dstar), _p(self.dz)), "reduced_frame")
+        self.nu = np.where((self.flags & PRED) != 0, self.dz - self.dhat, 0.0)
+
+    def predict_learned(self, left, T):
+        """Prediction step of a learned-window frame -> the network input
+        (float64 [H, W, 4], before rounding to bfloat16)."""
+        from . import cnn
+        if not self.started:
+            raise RuntimeError("reduced_frame before full_frame")
+        (self.dhat, self.pm, self.flags, self.lo, self.hi,
+         self.nu_w) = predict_aux(self.prm, self.d, self.p, self.sflags, T, self.nu)
+        return cnn.features(left, self.dhat, self.pm, self.flags, self.nu_w)
+
+    def finish_learned(self, left, right, hw, rpix, gate_rerun: bool):
+        """Rest of a learned-window frame after predict_learned(): windows
+        from the half-widths hw, matching, correction with the per-pixel
+        measurement variance rpix and, with gate_rerun, one more matching
+        pass in which the pixels that failed the innovation test search the
+        full range and restart from that measurement."""
+        self.hw, self.rpix = np.asarray(hw, np.float64), np.asarray(rpix, np.float64)
+        self.flags, self.lo, self.hi = learned_windows(self.prm, self.dhat, self.hw, self.flags, self.lo,
+                                                       self.hi)
+        self.dstar, self.dz = match(self.prm, left, right, self.lo, self.hi)
+        d, p, mask, sflags, nu = correct_ex(self.prm, self.dhat, self.pm, self.flags, self.lo, self.hi,
+                                            self.dstar, self.dz, self.rpix)
+        self.gatefail = mask.astype(bool)
+        if gate_rerun and self.gatefail.any():
+            D = self.prm.max_disp
+            self.flags = np.where(self.gatefail, self.flags | FULLWIN | GATEFAIL, self.flags).astype(np.uint8)
+            self.lo = np.where(self.gatefail, 0, self.lo).astype(np.int32)
+            self.hi = np.where(self.gatefail, D - 1, self.hi).astype(np.int32)
+            self.dstar, self.dz = match(self.prm, left, right, self.lo, self.hi)
+            d, p, mask, sflags, nu = correct_ex(self.prm, self.dhat, self.pm, self.flags, self.lo, self.hi,
+                                                self.dstar, self.dz, self.rpix)
+        self.d, self.p, self.mask, self.sflags, self.nu = d, p, mask, sflags, nu
+
+    def learned_frame(self, left, right, T, theta, gate_rerun: bool = True):
+        """A whole learned-window frame with the fp64 network of oracle.cnn
+        applied to the bfloat16-rounded input."""
+        from . import cnn
+        f = self.predict_learned(left, T)
+        o, _ = cnn.forward(theta, cnn.bf16_round(f)[None])
+        hw, rpix = cnn.head(o[0], self.prm.k_sigma)
+        self.finish_learned(left, right, hw, rpix, gate_rerun)
 
     def set_state(self, d, p, sflags):
         self.d[:] = d

@@ -291,6 +291,17 @@ done:
 int orc_predict(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
                 const double T[16], double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi)
 {
+    return orc_predict_aux(prm, d, p, sflags, NULL, T, dhat, pm, flags, lo, hi, NULL);
+}
+
+/* As orc_predict; in addition, when aux_src and aux_out are given, a target
+ * whose warp winner is source s receives aux_out = aux_src[s] (the learned
+ * window's "previous innovation" input travels with the winner); filled
+ * holes and targets without a prediction receive 0. */
+int orc_predict_aux(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
+                    const double *aux_src, const double T[16], double *dhat, double *pm, uint8_t *flags,
+                    int32_t *lo, int32_t *hi, double *aux_out)
+{
     int W = prm->width, H = prm->height, D = prm->max_disp;
     size_t n = (size_t)W * H;
     double f = prm->f, B = prm->baseline, cx = prm->cx, cy = prm->cy;
@@ -349,6 +360,10 @@ int orc_predict(const orc_params *prm, const double *d, const double *p, const u
     }
     for (size_t t = 0; t < n; t++)
         has[t] = win[t] >= 0;
+    if (aux_src && aux_out) {
+        for (size_t t = 0; t < n; t++)
+            aux_out[t] = win[t] >= 0 ? aux_src[win[t]] : 0.0;
+    }
     /* zooming-hole fill from the winners */
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
@@ -423,6 +438,8 @@ int orc_predict(const orc_params *prm, const double *d, const double *p, const u
         if (!ok) {
             dhat[t] = 0.0;
             pm[t] = 0.0;
+            if (aux_src && aux_out)
+                aux_out[t] = 0.0;
         }
         flags[t] = fl;
     }
@@ -447,9 +464,24 @@ int orc_correct(const orc_params *prm, const double *dhat, const double *pm, con
                 const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                 double *d, double *p, uint8_t *mask, uint8_t *sflags)
 {
+    return orc_correct_ex(prm, dhat, pm, flags, lo, hi, dstar, dz, NULL, d, p, mask, sflags, NULL);
+}
+
+/* As orc_correct, with
+ *  - rpix: per-pixel measurement variance r of the learned window (NULL:
+ *    prm->r everywhere); a restart from the measurement always takes prm->r;
+ *  - nu_out: the innovation dz - dhat of pixels with a prediction, 0
+ *    elsewhere (NULL: not written);
+ *  - ORC_GATEFAIL pixels (re-measured over the full range after failing the
+ *    innovation test of a first pass, FULLWIN also set): restart from the
+ *    measurement, stay marked moving, RESET for the next frame. */
+int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
+                   const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
+                   const double *rpix, double *d, double *p, uint8_t *mask, uint8_t *sflags, double *nu_out)
+{
     int n = prm->width * prm->height, D = prm->max_disp;
-    double r = prm->r;
     for (int t = 0; t < n; t++) {
+        double r = rpix ? rpix[t] : prm->r;
         int moving = 0;
         double nu = 0.0, S = 0.0;
         if (flags[t] & ORC_PRED) {
@@ -457,9 +489,18 @@ int orc_correct(const orc_params *prm, const double *dhat, const double *pm, con
             S = pm[t] + r;
             moving = (nu * nu) / S > prm->chi2_gate;
         }
+        if (nu_out)
+            nu_out[t] = nu;
+        if (flags[t] & ORC_GATEFAIL) {
+            d[t] = dz[t];
+            p[t] = prm->r;
+            mask[t] = 1;
+            sflags[t] = ORC_RESET;
+            continue;
+        }
         if (flags[t] & ORC_FULLWIN) {
             d[t] = dz[t];
-            p[t] = r;
+            p[t] = prm->r;
         } else {
             double K = pm[t] / S;
             double a = 1.0 - K;
@@ -469,6 +510,30 @@ int orc_correct(const orc_params *prm, const double *dhat, const double *pm, con
         int sat = (dstar[t] == lo[t] && lo[t] > 0) || (dstar[t] == hi[t] && hi[t] < D - 1);
         mask[t] = (uint8_t)moving;
         sflags[t] = (uint8_t)((moving || sat) ? ORC_RESET : 0);
+    }
+    return 0;
+}
+
+/* Learned search windows: a pixel that still has a finite window after the
+ * prediction gets [floor(dhat - w), ceil(dhat + w)] clipped to [0, D-1],
+ * with w its predicted half-width; w >= ORC_LEARNED_WMAX (or NaN) sends it to
+ * the full range (FULLWIN). */
+int orc_learned_windows(const orc_params *prm, const double *dhat, const double *hw, uint8_t *flags,
+                        int32_t *lo, int32_t *hi)
+{
+    int n = prm->width * prm->height, D = prm->max_disp;
+    for (int t = 0; t < n; t++) {
+        if (flags[t] & ORC_FULLWIN)
+            continue;
+        if (!(hw[t] < ORC_LEARNED_WMAX)) {
+            flags[t] |= ORC_FULLWIN;
+            lo[t] = 0;
+            hi[t] = D - 1;
+            continue;
+        }
+        int l = (int)floor(dhat[t] - hw[t]), h = (int)ceil(dhat[t] + hw[t]);
+        lo[t] = l < 0 ? 0 : l;
+        hi[t] = h > D - 1 ? D - 1 : h;
     }
     return 0;
 }

@@ -17,6 +17,8 @@ extern "C" {
 #define ORC_PRED 1u     /* a prediction (warp winner or filled hole) survived */
 #define ORC_RESET 2u    /* full-range search forced by the previous frame */
 #define ORC_FULLWIN 4u  /* this frame searched [0, D-1] */
+#define ORC_GATEFAIL 8u /* re-measured over [0, D-1] after failing the innovation test */
+#define ORC_LEARNED_WMAX 32.0   /* a learned half-width at or above this means "full range" */
 
 typedef struct {
     int32_t width, height, max_disp;
@@ -39,6 +41,14 @@ int orc_match(const orc_params *prm, const uint8_t *left, const uint8_t *right,
               int32_t *C_out, int32_t *S_out);
 int orc_predict(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
                 const double T[16], double *dhat, double *pm, uint8_t *flags, int32_t *lo, int32_t *hi);
+int orc_predict_aux(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
+                    const double *aux_src, const double T[16], double *dhat, double *pm, uint8_t *flags,
+                    int32_t *lo, int32_t *hi, double *aux_out);
+int orc_learned_windows(const orc_params *prm, const double *dhat, const double *hw, uint8_t *flags,
+                        int32_t *lo, int32_t *hi);
+int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
+                   const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
+                   const double *rpix, double *d, double *p, uint8_t *mask, uint8_t *sflags, double *nu_out);
 int orc_correct(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
                 const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                 double *d, double *p, uint8_t *mask, uint8_t *sflags);
