@@ -47,6 +47,13 @@ extern "C" {
 #define SGM_FLAG_PRED 1u     /* a prediction exists (splat winner or filled hole) */
 #define SGM_FLAG_RESET 2u    /* previous frame forced a full-range search here */
 #define SGM_FLAG_FULLWIN 4u  /* this frame searched [0, max_disp-1] */
+#define SGM_FLAG_GATEFAIL 8u /* failed the innovation test, re-measured over the full range (gate_rerun) */
+
+/* search-window rules (sgm_params.window_mode) */
+#define SGM_WIN_KSIGMA 0     /* d^ -+ k_sigma * sqrt(p^-), rounded outward (Section 2.4) */
+#define SGM_WIN_LEARNED 1    /* half-width and measurement variance from the window network */
+#define SGM_LEARNED_WMAX 32  /* a learned half-width >= this searches the full range */
+#define SGM_CNN_NPARAMS 19394
 
 typedef struct sgm_context sgm_context;
 
@@ -62,11 +69,16 @@ typedef struct {
     double chi2_gate;           /* innovation test threshold on nu^2 / (p^- + r) */
     double disc_thresh;         /* discontinuity rejection threshold (px) */
     double f, cx, cy, baseline; /* focal length (px), principal point (px), baseline (m) */
+    int32_t window_mode;        /* SGM_WIN_KSIGMA or SGM_WIN_LEARNED */
+    int32_t gate_rerun;         /* 1: pixels failing the innovation test are matched again over
+                                   the full range in the same frame and restart from that
+                                   measurement (the frame is matched twice) */
 } sgm_params;
 
 /* Fill `out` with the defaults for a width x height x max_disp problem:
  * census 9x7, 8 paths, P1=7, P2=86, k_sigma=3, q=0.5, r=1, chi2 99% (1 dof),
- * disc_thresh=2, f=0.58*width, principal point at the image centre, B=0.54. */
+ * disc_thresh=2, f=0.58*width, principal point at the image centre, B=0.54,
+ * SGM_WIN_KSIGMA windows, no gate re-run. */
 int sgm_default_params(sgm_params *out, int32_t width, int32_t height, int32_t max_disp);
 
 /* Validate `prm` and allocate a context with every device buffer it will
@@ -130,12 +142,23 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
  *   SGM_STAGE_FLAGS          uint8 per pixel (SGM_FLAG_*)
  *   SGM_STAGE_DSTAR          int32 per pixel;  SGM_STAGE_DZ float64 per pixel
  *   SGM_STAGE_STATUS         uint32: number of windows clamped by match_windows
+ *   SGM_STAGE_NU             float64 per pixel: innovation dz - d^ of the last
+ *                            frame (0 where there was no prediction)
+ *   SGM_STAGE_NU_W           float64 per pixel: the previous innovation of the
+ *                            pixel's warp winner (0 for filled holes / none)
+ * learned windows (SGM_WIN_LEARNED contexts, last reduced frame):
+ *   SGM_STAGE_FEATURES       bfloat16 [4] per pixel: network input
+ *   SGM_STAGE_CNN_OUT        float32 [2] per pixel: network output
+ *   SGM_STAGE_HALFWIDTH      float32 per pixel: half-width w
+ *   SGM_STAGE_RPIX           float32 per pixel: measurement variance r
  * sgm_cost_cells() synchronises the stream and returns the cell count M. */
 enum {
     SGM_STAGE_CENSUS_L = 0, SGM_STAGE_CENSUS_R, SGM_STAGE_LO, SGM_STAGE_HI, SGM_STAGE_OFFSETS,
     SGM_STAGE_COST, SGM_STAGE_SUM, SGM_STAGE_DHAT, SGM_STAGE_PM, SGM_STAGE_FLAGS,
     SGM_STAGE_DSTAR, SGM_STAGE_DZ, SGM_STAGE_STATUS,
-    SGM_STAGE_PATH0 = 16
+    SGM_STAGE_PATH0 = 16,
+    SGM_STAGE_NU = 32, SGM_STAGE_NU_W, SGM_STAGE_FEATURES, SGM_STAGE_CNN_OUT, SGM_STAGE_HALFWIDTH,
+    SGM_STAGE_RPIX
 };
 int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream);
 int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
@@ -149,9 +172,81 @@ int sgm_set_debug(sgm_context *ctx, int32_t on);
  * then writes the accumulated milliseconds of each stage (SGM_PROF_COUNT
  * doubles, in the order of the enum) and the number of frames measured. */
 enum { SGM_PROF_CENSUS = 0, SGM_PROF_PREDICT, SGM_PROF_COST, SGM_PROF_AGG_H, SGM_PROF_AGG_V, SGM_PROF_WTA,
-       SGM_PROF_COUNT };   /* AGG_H: horizontal paths (timed on an internal stream); AGG_V: the others */
+       SGM_PROF_CNN, SGM_PROF_RERUN, SGM_PROF_COUNT };
+/* AGG_H: horizontal paths (timed on an internal stream); AGG_V: the others;
+ * CNN: learned-window input, network and head; RERUN: the whole second
+ * matching pass of gate_rerun */
 int sgm_set_profiling(sgm_context *ctx, int32_t on);
 int sgm_read_profile(sgm_context *ctx, double *ms, int64_t *frames, void *stream);
+
+/* ---- learned search window --------------------------------------------------
+ * Extension of the method: instead of d^ -+ k sigma, a five-layer 3x3
+ * convolutional network (channels 4 -> 16 -> 32 -> 32 -> 16 -> 2, ReLU
+ * between layers, zero padding, bfloat16 weights and activations with fp32
+ * accumulation) reads per pixel
+ *   [d^ / 64, min(p^-, 16) / 4, (|dI/dx| + |dI/dy|) / 256, min(|nu_w|, 8) / 4]
+ * (central differences of the left image, neighbours clamped; without a
+ * prediction the first two are 0 and 4) and outputs o = (o0, o1):
+ *   w = max(1, k_sigma * exp(o0 / 2))       (o0: log-variance of d_full - d^)
+ *   r = clamp(exp(o1), 1/16, 64)            (o1: log measurement variance)
+ * A pixel with a finite window searches [floor(d^ - w), ceil(d^ + w)]
+ * (clipped to [0, max_disp-1]); w >= SGM_LEARNED_WMAX searches the full
+ * range.  The Kalman update and the innovation test use r per pixel; a
+ * restart from the measurement uses params.r.
+ *
+ * Parameters: SGM_CNN_NPARAMS floats, layer by layer W[co][ky][kx][ci] then
+ * b[co] (ci, co of the five layers as above).
+ *
+ * sgm_set_window_model: HOST parameter vector for a SGM_WIN_LEARNED context
+ *   (copied; synchronous).  SGM_ESTATE from sgm_reduced_frame of a learned
+ *   context without a model.
+ * sgm_get_features: the network input of the context's last predicted frame
+ *   (its prediction and innovation) for the given left image, as bfloat16
+ *   [N][4] into `out` (device); any window mode.
+ * sgm_learned_targets: training targets of the context's last predicted
+ *   frame, float [N][4] (e, m, we, wm) into `out` (device):
+ *   e = clip(dz_full - d^, +-16), m = clip(dz_full - gt, +-16),
+ *   we = [prediction], wm = we * [gt >= 0]; dz_full (float64) is the
+ *   full-range measurement of the same frame, gt (float32) the reference
+ *   disparity, negative where unknown; all device pointers, N entries,
+ *   `out` 16-byte aligned. */
+int sgm_set_window_model(sgm_context *ctx, const float *params, int32_t n);
+int sgm_get_features(sgm_context *ctx, const uint8_t *left, int32_t pitch, uint16_t *out, void *stream);
+int sgm_learned_targets(sgm_context *ctx, const double *dz_full, const float *gt, float *out, void *stream);
+
+/* ---- training the window network ------------------------------------------
+ * A trainer holds fp32 parameters, Adam moments (b1 0.9, b2 0.999, eps 1e-8)
+ * and buffers for batches of up to max_images images of height x width.
+ * Inputs x are bfloat16 [nimg][height][width][4] (device, 8-byte aligned),
+ * outputs float [..][2].  Loss (targets float [..][4] = e, m, we, wm as from
+ * sgm_learned_targets, 16-byte aligned):
+ *   L = sum we (o0 + e^2 exp(-o0)) / 2 / max(1, sum we)
+ *     + sum wm (o1 + m^2 exp(-o1)) / 2 / max(1, sum wm),
+ * o clipped to [-15, 15] (zero gradient outside).
+ *
+ * sgm_cnn_set_params / _get_params: HOST vectors of SGM_CNN_NPARAMS floats;
+ *   set also clears the Adam moments and step count; both synchronise.
+ * sgm_cnn_forward: o for x into `out` (device, may be NULL; the trainer keeps
+ *   the activations for the next backward).
+ * sgm_cnn_loss: L into *loss (device float) and dL/do into the trainer, for
+ *   the last forward.
+ * sgm_cnn_backward: parameter gradient of sum(dL/do * o) for the last
+ *   forward and loss, kept in the trainer (fixed-order sums: deterministic).
+ * sgm_cnn_get_grads: HOST copy of that gradient (synchronises).
+ * sgm_cnn_adam: one Adam step with learning rate lr from that gradient.
+ * sgm_cnn_train_step: forward, loss, backward and Adam in one call. */
+typedef struct sgm_cnn sgm_cnn;
+int sgm_cnn_create(int32_t max_images, int32_t height, int32_t width, sgm_cnn **out);
+void sgm_cnn_destroy(sgm_cnn *t);
+int sgm_cnn_set_params(sgm_cnn *t, const float *params, int32_t n);
+int sgm_cnn_get_params(sgm_cnn *t, float *params, int32_t n);
+int sgm_cnn_forward(sgm_cnn *t, const uint16_t *x, int32_t nimg, float *out, void *stream);
+int sgm_cnn_loss(sgm_cnn *t, const float *targets, float *loss, void *stream);
+int sgm_cnn_backward(sgm_cnn *t, void *stream);
+int sgm_cnn_get_grads(sgm_cnn *t, float *grads, int32_t n);
+int sgm_cnn_adam(sgm_cnn *t, float lr, void *stream);
+int sgm_cnn_train_step(sgm_cnn *t, const uint16_t *x, const float *targets, int32_t nimg, float lr,
+                       float *loss, void *stream);
 
 /* ---- batches of independent stereo streams --------------------------------
  * A batch owns one context per stream (uneven sizes and disparity ranges are

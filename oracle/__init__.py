@@ -376,4 +376,5 @@ class OracleFilter:
         self.d[:] = d
         self.p[:] = p
         self.sflags[:] = sflags
+        self.nu[:] = 0.0
         self.started = True

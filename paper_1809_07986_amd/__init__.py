@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["ReducedSGM", "SgmBatch", "SgmError", "default_params", "as_matrix"]
+__all__ = ["ReducedSGM", "SgmBatch", "CnnTrainer", "SgmError", "default_params", "as_matrix", "load_window_model"]
 
 
 class SgmError(RuntimeError):
@@ -181,17 +181,23 @@ class ReducedSGM:
                  N.STAGE_HI: torch.int32, N.STAGE_OFFSETS: torch.int32, N.STAGE_COST: torch.uint8,
                  N.STAGE_SUM: torch.int16, N.STAGE_DHAT: torch.float64, N.STAGE_PM: torch.float64,
                  N.STAGE_FLAGS: torch.uint8, N.STAGE_DSTAR: torch.int32, N.STAGE_DZ: torch.float64,
-                 N.STAGE_STATUS: torch.int32}
+                 N.STAGE_STATUS: torch.int32, N.STAGE_NU: torch.float64, N.STAGE_NU_W: torch.float64,
+                 N.STAGE_FEATURES: torch.int16, N.STAGE_CNN_OUT: torch.float32, N.STAGE_HALFWIDTH: torch.float32,
+                 N.STAGE_RPIX: torch.float32}
 
     def stage(self, stage: int) -> torch.Tensor:
         """Intermediate result of the last frame (see include/sgm.h)."""
         npx = self.H * self.W
-        if stage in (N.STAGE_COST, N.STAGE_SUM) or stage >= N.STAGE_PATH0:
+        if stage in (N.STAGE_COST, N.STAGE_SUM) or N.STAGE_PATH0 <= stage < N.STAGE_PATH0 + 8:
             count = self.cost_cells()
         elif stage == N.STAGE_OFFSETS:
             count = npx + 1
         elif stage == N.STAGE_STATUS:
             count = 1
+        elif stage == N.STAGE_FEATURES:
+            count = npx * 4
+        elif stage == N.STAGE_CNN_OUT:
+            count = npx * 2
         else:
             count = npx
         dt = self._STAGE_DT.get(stage, torch.uint8)
@@ -199,7 +205,115 @@ class ReducedSGM:
         _check(_lib().sgm_get_stage(self._h, stage, _ptr(out), out.numel() * out.element_size(), _stream()))
         if count == npx:
             out = out.view(self.H, self.W)
+        elif stage in (N.STAGE_FEATURES, N.STAGE_CNN_OUT):
+            out = out.view(self.H, self.W, -1)
         return out
+
+    # -- learned search window --------------------------------------------------
+    def set_window_model(self, params):
+        """Network parameters (CNN_NPARAMS floats, layout of include/sgm.h)."""
+        arr = np.ascontiguousarray(params, np.float32).reshape(-1)
+        with torch.cuda.device(self.device):
+            _check(_lib().sgm_set_window_model(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                               arr.size))
+
+    def features(self, left) -> torch.Tensor:
+        """bfloat16 network input [H, W, 4] (as int16 bit patterns) of the last predicted frame."""
+        l = _dev_image(left, self.device)
+        out = torch.empty((self.H, self.W, 4), dtype=torch.int16, device=self.device)
+        _check(_lib().sgm_get_features(self._h, _ptr(l), l.shape[1], _ptr(out), _stream()))
+        self._keep = (l,)
+        return out
+
+    def learned_targets(self, dz_full: torch.Tensor, gt: torch.Tensor) -> torch.Tensor:
+        """float [H, W, 4] (e, m, we, wm) of the last predicted frame."""
+        dz = dz_full.to(self.device, torch.float64).contiguous()
+        g = gt.to(self.device, torch.float32).contiguous()
+        out = torch.empty((self.H, self.W, 4), dtype=torch.float32, device=self.device)
+        _check(_lib().sgm_learned_targets(self._h, _ptr(dz), _ptr(g), _ptr(out), _stream()))
+        self._keep = (dz, g)
+        return out
+
+
+def load_window_model(path: Optional[str] = None) -> np.ndarray:
+    """Parameters of the trained window network shipped with the package."""
+    import os
+    if path is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "window_cnn.f32")
+    arr = np.fromfile(path, dtype="<f4")
+    if arr.size != N.CNN_NPARAMS:
+        raise ValueError(f"{path}: {arr.size} floats, expected {N.CNN_NPARAMS}")
+    return arr
+
+
+class CnnTrainer:
+    """Trainer of the window network (library kernels for every step)."""
+
+    def __init__(self, max_images: int, height: int, width: int, device: Optional[torch.device] = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.H, self.W, self.maxn = height, width, max_images
+        with torch.cuda.device(self.device):
+            h = ctypes.c_void_p()
+            _check(_lib().sgm_cnn_create(max_images, height, width, ctypes.byref(h)))
+        self._h = h
+        self.loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                _lib().sgm_cnn_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        arr = np.ascontiguousarray(params, np.float32).reshape(-1)
+        _check(_lib().sgm_cnn_set_params(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), arr.size))
+
+    def get_params(self) -> np.ndarray:
+        arr = np.zeros(N.CNN_NPARAMS, np.float32)
+        _check(_lib().sgm_cnn_get_params(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), arr.size))
+        return arr
+
+    def _x(self, x: torch.Tensor) -> torch.Tensor:
+        if x.dtype != torch.int16 or x.dim() != 4 or x.shape[1:] != (self.H, self.W, 4):
+            raise ValueError("x must be int16 (bfloat16 bits) [n, H, W, 4]")
+        return x.contiguous()
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        x = self._x(x)
+        out = torch.empty((x.shape[0], self.H, self.W, 2), dtype=torch.float32, device=self.device)
+        _check(_lib().sgm_cnn_forward(self._h, _ptr(x), x.shape[0], _ptr(out), _stream()))
+        self._keep = (x,)
+        return out
+
+    def loss_grad(self, targets: torch.Tensor) -> torch.Tensor:
+        """Loss of the last forward (device scalar) and its parameter gradient."""
+        t = targets.to(self.device, torch.float32).contiguous()
+        _check(_lib().sgm_cnn_loss(self._h, _ptr(t), _ptr(self.loss), _stream()))
+        _check(_lib().sgm_cnn_backward(self._h, _stream()))
+        self._keep_t = t
+        return self.loss
+
+    def grads(self) -> np.ndarray:
+        arr = np.zeros(N.CNN_NPARAMS, np.float32)
+        _check(_lib().sgm_cnn_get_grads(self._h, arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), arr.size))
+        return arr
+
+    def adam(self, lr: float):
+        _check(_lib().sgm_cnn_adam(self._h, float(lr), _stream()))
+
+    def train_step(self, x: torch.Tensor, targets: torch.Tensor, lr: float) -> torch.Tensor:
+        x = self._x(x)
+        t = targets.contiguous()
+        _check(_lib().sgm_cnn_train_step(self._h, _ptr(x), _ptr(t), x.shape[0], float(lr), _ptr(self.loss),
+                                         _stream()))
+        self._keep = (x, t)
+        return self.loss
 
 
 class SgmBatch:

@@ -12,10 +12,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsgm.so")
 
 SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_ESTATE = 0, -1, -2, -3, -4
-FLAG_PRED, FLAG_RESET, FLAG_FULLWIN = 1, 2, 4
+FLAG_PRED, FLAG_RESET, FLAG_FULLWIN, FLAG_GATEFAIL = 1, 2, 4, 8
+WIN_KSIGMA, WIN_LEARNED = 0, 1
+LEARNED_WMAX = 32
+CNN_NPARAMS = 19394
 (STAGE_CENSUS_L, STAGE_CENSUS_R, STAGE_LO, STAGE_HI, STAGE_OFFSETS, STAGE_COST, STAGE_SUM, STAGE_DHAT,
  STAGE_PM, STAGE_FLAGS, STAGE_DSTAR, STAGE_DZ, STAGE_STATUS) = range(13)
 STAGE_PATH0 = 16
+(STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX) = range(32, 38)
 
 # every symbol include/sgm.h declares
 EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
@@ -23,8 +27,10 @@ EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", 
            "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
            "sgm_read_profile", "sgm_batch_create", "sgm_batch_destroy", "sgm_batch_context", "sgm_batch_full",
            "sgm_batch_step", "sgm_batch_step_graph", "sgm_batch_set_schedule", "sgm_batch_autotune",
-           "sgm_last_error")
-PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta")
+           "sgm_set_window_model", "sgm_get_features", "sgm_learned_targets", "sgm_cnn_create", "sgm_cnn_destroy",
+           "sgm_cnn_set_params", "sgm_cnn_get_params", "sgm_cnn_forward", "sgm_cnn_loss", "sgm_cnn_backward",
+           "sgm_cnn_get_grads", "sgm_cnn_adam", "sgm_cnn_train_step", "sgm_last_error")
+PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta", "cnn", "rerun")
 
 
 class SgmParams(ctypes.Structure):
@@ -34,7 +40,7 @@ class SgmParams(ctypes.Structure):
                 ("k_sigma", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
                 ("chi2_gate", ctypes.c_double), ("disc_thresh", ctypes.c_double),
                 ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
-                ("baseline", ctypes.c_double)]
+                ("baseline", ctypes.c_double), ("window_mode", ctypes.c_int32), ("gate_rerun", ctypes.c_int32)]
 
 
 _lib = None
@@ -76,6 +82,19 @@ def load(path: str = LIB_PATH):
         "sgm_batch_step_graph": [P, ctypes.POINTER(ctypes.c_double), P],
         "sgm_batch_set_schedule": [P, I32, I32],
         "sgm_batch_autotune": [P, ctypes.POINTER(ctypes.c_double), I32, ctypes.POINTER(I32), P],
+        "sgm_set_window_model": [P, ctypes.POINTER(ctypes.c_float), I32],
+        "sgm_get_features": [P, P, I32, P, P],
+        "sgm_learned_targets": [P, P, P, P, P],
+        "sgm_cnn_create": [I32, I32, I32, ctypes.POINTER(P)],
+        "sgm_cnn_destroy": [P],
+        "sgm_cnn_set_params": [P, ctypes.POINTER(ctypes.c_float), I32],
+        "sgm_cnn_get_params": [P, ctypes.POINTER(ctypes.c_float), I32],
+        "sgm_cnn_forward": [P, P, I32, P, P],
+        "sgm_cnn_loss": [P, P, P, P],
+        "sgm_cnn_backward": [P, P],
+        "sgm_cnn_get_grads": [P, ctypes.POINTER(ctypes.c_float), I32],
+        "sgm_cnn_adam": [P, ctypes.c_float, P],
+        "sgm_cnn_train_step": [P, P, P, I32, ctypes.c_float, P, P],
         "sgm_last_error": [],
     }
     for name, args in sig.items():
@@ -84,6 +103,7 @@ def load(path: str = LIB_PATH):
         fn.restype = ctypes.c_int
     lib.sgm_destroy.restype = None
     lib.sgm_batch_destroy.restype = None
+    lib.sgm_cnn_destroy.restype = None
     lib.sgm_batch_context.restype = ctypes.c_void_p
     lib.sgm_last_error.restype = ctypes.c_char_p
     _lib = lib

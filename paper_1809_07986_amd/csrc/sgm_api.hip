@@ -34,6 +34,7 @@ struct sgm_context {
     Profiler prof;
     hipStream_t side;           // horizontal aggregation runs here, forked from the caller's stream
     hipEvent_t fork, join;
+    bool has_model;             // learned mode: sgm_set_window_model was called
 };
 
 namespace {
@@ -82,6 +83,10 @@ int validate(const sgm_params *p)
         return fail(SGM_EINVAL, "need k_sigma > 0, q >= 0, r > 0, chi2_gate > 0, disc_thresh >= 0");
     if (!(p->f > 0) || !(p->baseline > 0) || !isfinite(p->cx) || !isfinite(p->cy))
         return fail(SGM_EINVAL, "need f > 0, baseline > 0 and a finite principal point");
+    if (p->window_mode != SGM_WIN_KSIGMA && p->window_mode != SGM_WIN_LEARNED)
+        return fail(SGM_EINVAL, "window_mode %d is neither SGM_WIN_KSIGMA nor SGM_WIN_LEARNED", p->window_mode);
+    if (p->gate_rerun != 0 && p->gate_rerun != 1)
+        return fail(SGM_EINVAL, "gate_rerun must be 0 or 1 (got %d)", p->gate_rerun);
     return SGM_OK;
 }
 
@@ -96,7 +101,8 @@ void free_buffers(DevBuffers &b)
     void *all[] = {b.cen_l, b.cen_r, b.win,    b.off,    b.scan_part, b.cost,  b.lr,   b.sum,  b.d,   b.p,
                    b.sflags, b.mask, b.dhat,   b.pm,     b.flags,     b.dstar, b.dz,   b.zkey, b.zidx, b.tgt,
                    b.dprime, b.pprime, b.has, b.rw,     b.pred,      b.rst,   b.dw,   b.pw,   b.dfill, b.pfill,
-                   b.status};
+                   b.status, b.nu,   b.nu_w,   b.feat,   b.act_a,     b.act_b, b.cnn_out, b.hw, b.rpix, b.theta,
+                   b.frag};
     for (void *p : all)
         if (p)
             (void)hipFree(p);
@@ -152,6 +158,8 @@ hipError_t prof_flush(Profiler &pf)
     return hipSuccess;
 }
 
+Profiler g_noprof;   // never switched on: marks through it record nothing
+
 // mark the start / end of a stage of the current frame (no-op unless on)
 struct StageMark {
     Profiler &pf;
@@ -182,11 +190,13 @@ void prof_end_frame(Profiler &pf)
 }
 
 // census, cost, aggregation, WTA (+ filter update in modes 0 and 1)
-int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, int mode, hipStream_t s)
+int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, int mode, hipStream_t s,
+                bool marks = true)
 {
     const Geometry &g = ctx->g;
     DevBuffers &b = ctx->b;
-    StageMark mk(ctx->prof, s);
+    // stages of a second matching pass are timed as a whole by the caller
+    StageMark mk(marks ? ctx->prof : g_noprof, s);
     mk.begin(SGM_PROF_CENSUS);
     hipError_t e = launch_census(g, l, r, pitch, b.cen_l, b.cen_r, s);
     mk.end(SGM_PROF_CENSUS);
@@ -209,7 +219,7 @@ int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pi
             e = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
         if (e != hipSuccess)
             return hip_fail(e, "stream fork");
-        StageMark mh(ctx->prof, ctx->side);
+        StageMark mh(marks ? ctx->prof : g_noprof, ctx->side);
         mh.begin(SGM_PROF_AGG_H);
         e = launch_agg_h(g, b, ctx->side);
         mh.end(SGM_PROF_AGG_H);
@@ -229,7 +239,8 @@ int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pi
             return hip_fail(e, "stream join");
     }
     mk.begin(SGM_PROF_WTA);
-    e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, s);
+    const float *rpix = (mode == 1 && ctx->prm.window_mode == SGM_WIN_LEARNED) ? b.rpix : nullptr;
+    e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, rpix, s);
     mk.end(SGM_PROF_WTA);
     if (e != hipSuccess)
         return hip_fail(e, "wta launch");
@@ -252,22 +263,58 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
     wc.fB = p.f * p.baseline;
     wc.zmin = 1e-9 * wc.fB;
     wc.q = p.q;
+    const bool learned = p.window_mode == SGM_WIN_LEARNED;
+    if (learned && !ctx->has_model)
+        return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
     prof_begin_frame(ctx->prof, s);
     StageMark mk(ctx->prof, s);
     mk.begin(SGM_PROF_PREDICT);
-    hipError_t e = launch_predict(ctx->g, ctx->b, wc, Tdev, correct_const(p), s);
+    hipError_t e = launch_predict_core(ctx->g, ctx->b, wc, Tdev, correct_const(p), s);
     mk.end(SGM_PROF_PREDICT);
     if (e != hipSuccess)
         return hip_fail(e, "prediction launch");
+    if (learned) {
+        // network input -> network -> half-widths, variances and windows
+        const Geometry &g = ctx->g;
+        DevBuffers &b = ctx->b;
+        mk.begin(SGM_PROF_CNN);
+        e = launch_features(g, b, left, pitch, b.feat, s);
+        if (e == hipSuccess)
+            e = cnn_forward(b.theta, b.frag, b.feat, 1, g.H, g.W, b.act_a, b.act_b, b.act_a, b.act_b, b.cnn_out, s);
+        if (e == hipSuccess)
+            e = launch_head(g, b, (float)p.k_sigma, s);
+        mk.end(SGM_PROF_CNN);
+        if (e != hipSuccess)
+            return hip_fail(e, "window network launch");
+    }
+    e = launch_scan(ctx->g, ctx->b, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "offset scan launch");
     int rc = run_matcher(ctx, left, right, pitch, 1, s);
     if (rc)
         return rc;
+    if (p.gate_rerun) {
+        // pixels that failed the innovation test search the full range in a
+        // second matching pass and restart from its measurement
+        mk.begin(SGM_PROF_RERUN);
+        e = launch_gate_widen(ctx->g, ctx->b, s);
+        if (e == hipSuccess)
+            e = launch_scan(ctx->g, ctx->b, s);
+        if (e != hipSuccess)
+            return hip_fail(e, "gate re-run launch");
+        rc = run_matcher(ctx, left, right, pitch, 1, s, false);
+        mk.end(SGM_PROF_RERUN);
+        if (rc)
+            return rc;
+    }
     prof_end_frame(ctx->prof);
     return SGM_OK;
 }
 
 int full_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *right, int32_t pitch, hipStream_t s)
 {
+    if (ctx->prm.window_mode == SGM_WIN_LEARNED && !ctx->has_model)
+        return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
     prof_begin_frame(ctx->prof, s);
     hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
     if (e != hipSuccess)
@@ -384,6 +431,18 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.dfill, N));
     A(dalloc(&b.pfill, N));
     A(dalloc(&b.status, 4));
+    A(dalloc(&b.nu, N));
+    A(dalloc(&b.nu_w, N));
+    if (prm->window_mode == SGM_WIN_LEARNED) {
+        A(dalloc(&b.feat, N * 4));
+        A(dalloc(&b.act_a, N * 32));
+        A(dalloc(&b.act_b, N * 32));
+        A(dalloc(&b.cnn_out, N * 2));
+        A(dalloc(&b.hw, N));
+        A(dalloc(&b.rpix, N));
+        A(dalloc(&b.theta, (size_t)SGM_CNN_NPARAMS));
+        A(dalloc(&b.frag, cnn_frag_count()));
+    }
     if (e != hipSuccess) {
         free_buffers(b);
         delete ctx;
@@ -401,6 +460,8 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(hipMemset(b.pm, 0, N * sizeof(double)));
     A(hipMemset(b.off, 0, (N + 1) * sizeof(uint32_t)));
     A(hipMemset(b.status, 0, sizeof(uint32_t)));
+    A(hipMemset(b.nu, 0, N * sizeof(double)));
+    A(hipMemset(b.nu_w, 0, N * sizeof(double)));
     A(hipDeviceSynchronize());
     if (e != hipSuccess) {
         free_buffers(b);
@@ -419,6 +480,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     }
     ctx->started = false;
     ctx->debug = false;
+    ctx->has_model = false;
     *out = ctx;
     return SGM_OK;
 }
@@ -512,6 +574,8 @@ int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
             return fail(SGM_EINVAL, "T_k_km1[%d] is not finite", i);
     if (!ctx->started)
         return fail(SGM_ESTATE, "reduced frame requested before a full frame or set_state");
+    if (ctx->prm.window_mode == SGM_WIN_LEARNED && !ctx->has_model)
+        return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
     return reduced_frame_impl(ctx, left, right, pitch, T, nullptr, as_stream(stream));
 }
 
@@ -603,6 +667,8 @@ int sgm_set_state(sgm_context *ctx, const double *d, const double *p, const uint
         e = hipMemcpyAsync(ctx->b.p, p, N * sizeof(double), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->b.sflags, sflags, N, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(ctx->b.nu, 0, N * sizeof(double), s);
     if (e != hipSuccess)
         return hip_fail(e, "state copy");
     ctx->started = true;
@@ -641,7 +707,8 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
     const void *src = nullptr;
     size_t need = 0;
     size_t M = 0;
-    if (stage == SGM_STAGE_COST || stage == SGM_STAGE_SUM || stage >= SGM_STAGE_PATH0) {
+    if (stage == SGM_STAGE_COST || stage == SGM_STAGE_SUM ||
+        (stage >= SGM_STAGE_PATH0 && stage < SGM_STAGE_PATH0 + 8)) {
         int64_t m = 0;
         rc = sgm_cost_cells(ctx, &m, stream);
         if (rc)
@@ -666,6 +733,19 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
     case SGM_STAGE_DSTAR: src = b.dstar; need = N * 4; break;
     case SGM_STAGE_DZ: src = b.dz; need = N * 8; break;
     case SGM_STAGE_STATUS: src = b.status; need = 4; break;
+    case SGM_STAGE_NU: src = b.nu; need = N * 8; break;
+    case SGM_STAGE_NU_W: src = b.nu_w; need = N * 8; break;
+    case SGM_STAGE_FEATURES:
+    case SGM_STAGE_CNN_OUT:
+    case SGM_STAGE_HALFWIDTH:
+    case SGM_STAGE_RPIX:
+        if (ctx->prm.window_mode != SGM_WIN_LEARNED)
+            return fail(SGM_EINVAL, "stage %d exists in learned-window contexts only", stage);
+        src = stage == SGM_STAGE_FEATURES ? (const void *)b.feat
+              : stage == SGM_STAGE_CNN_OUT ? (const void *)b.cnn_out
+              : stage == SGM_STAGE_HALFWIDTH ? (const void *)b.hw : (const void *)b.rpix;
+        need = stage == SGM_STAGE_FEATURES || stage == SGM_STAGE_CNN_OUT ? N * 8 : N * 4;
+        break;
     case SGM_STAGE_LO:
     case SGM_STAGE_HI: {
         if (bytes != N * 4)
@@ -715,7 +795,7 @@ struct sgm_batch {
     const uint8_t **left = nullptr, **right = nullptr;
     int32_t *pitch = nullptr;
     double *Tdev = nullptr;                 // n x 16, device
-    double *save_d = nullptr, *save_p = nullptr;   // state save area for autotuning
+    double *save_d = nullptr, *save_p = nullptr, *save_nu = nullptr;   // state save area for autotuning
     uint8_t *save_f = nullptr, *save_m = nullptr;
     size_t *save_off = nullptr;             // per-stream offsets into the save area
     int nlanes = 1;
@@ -811,7 +891,8 @@ void batch_free(sgm_batch *b)
     }
     if (b->fork)
         (void)hipEventDestroy(b->fork);
-    for (void *p : {(void *)b->Tdev, (void *)b->save_d, (void *)b->save_p, (void *)b->save_f, (void *)b->save_m})
+    for (void *p : {(void *)b->Tdev, (void *)b->save_d, (void *)b->save_p, (void *)b->save_f, (void *)b->save_m,
+                    (void *)b->save_nu})
         if (p)
             (void)hipFree(p);
     delete[] b->ctx;
@@ -883,6 +964,8 @@ int sgm_batch_create(int32_t n, const sgm_params *params, const uint8_t *const *
         e = hipMalloc((void **)&b->save_f, tot);
     if (e == hipSuccess)
         e = hipMalloc((void **)&b->save_m, tot);
+    if (e == hipSuccess)
+        e = hipMalloc((void **)&b->save_nu, sizeof(double) * tot);
     for (int l = 0; l < kMaxLanes && e == hipSuccess; l++) {
         e = hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking);
         if (e == hipSuccess)
@@ -978,6 +1061,8 @@ int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *cho
             e = hipMemcpyAsync(b->save_f + b->save_off[i], b->ctx[i]->b.sflags, N, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->save_m + b->save_off[i], b->ctx[i]->b.mask, N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->save_nu + b->save_off[i], b->ctx[i]->b.nu, N * 8, hipMemcpyDeviceToDevice, s);
     }
     if (e != hipSuccess)
         return hip_fail(e, "state save");
@@ -1031,6 +1116,8 @@ int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *cho
             e = hipMemcpyAsync(b->ctx[i]->b.sflags, b->save_f + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess)
             e = hipMemcpyAsync(b->ctx[i]->b.mask, b->save_m + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->ctx[i]->b.nu, b->save_nu + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
     }
     if (e != hipSuccess)
         return hip_fail(e, "state restore");
@@ -1041,6 +1128,288 @@ int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *cho
         chosen[1] = best_o;
     }
     return SGM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// learned search window: model, network input, training targets, trainer
+// ---------------------------------------------------------------------------
+
+struct sgm_cnn {
+    int maxn, H, W;
+    int device;
+    int nimg;            // images of the last forward
+    bool have_loss;
+    int step;            // Adam steps taken
+    float *theta, *m, *v, *grad;
+    uint64_t *frag;
+    const uint16_t *x;   // input of the last forward (caller's buffer)
+    uint16_t *a1, *a2, *a3, *a4;
+    uint16_t *g0, *g1, *dz5;
+    float *out, *cnt, *part, *lpart;
+};
+
+namespace {
+
+void cnn_free(sgm_cnn *t)
+{
+    void *all[] = {t->theta, t->m, t->v, t->grad, t->frag, t->a1, t->a2, t->a3, t->a4,
+                   t->g0,    t->g1, t->dz5, t->out, t->cnt, t->part, t->lpart};
+    for (void *p : all)
+        if (p)
+            (void)hipFree(p);
+}
+
+int check_cnn(sgm_cnn *t)
+{
+    if (!t)
+        return fail(SGM_EINVAL, "trainer is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != t->device)
+        return fail(SGM_EINVAL, "trainer was created on device %d but device %d is current", t->device, dev);
+    return SGM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgm_set_window_model(sgm_context *ctx, const float *params, int32_t n)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (ctx->prm.window_mode != SGM_WIN_LEARNED)
+        return fail(SGM_EINVAL, "context was not created with window_mode SGM_WIN_LEARNED");
+    if (!params || n != SGM_CNN_NPARAMS)
+        return fail(SGM_EINVAL, "need %d parameters (got %d)", SGM_CNN_NPARAMS, n);
+    for (int i = 0; i < n; i++)
+        if (!isfinite(params[i]))
+            return fail(SGM_EINVAL, "parameter %d is not finite", i);
+    hipError_t e = hipMemcpy(ctx->b.theta, params, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = cnn_pack(ctx->b.theta, ctx->b.frag, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(e, "window model upload");
+    ctx->has_model = true;
+    return SGM_OK;
+}
+
+int sgm_get_features(sgm_context *ctx, const uint8_t *left, int32_t pitch, uint16_t *out, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!left || !out || pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "bad image, pitch or output");
+    hipError_t e = launch_features(ctx->g, ctx->b, left, pitch, out, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "feature launch");
+}
+
+int sgm_learned_targets(sgm_context *ctx, const double *dz_full, const float *gt, float *out, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!dz_full || !gt || !out)
+        return fail(SGM_EINVAL, "NULL pointer");
+    hipError_t e = launch_targets(ctx->g, ctx->b, dz_full, gt, out, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "target launch");
+}
+
+int sgm_cnn_create(int32_t max_images, int32_t height, int32_t width, sgm_cnn **out)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_images < 1 || height < 1 || width < 1 || (int64_t)max_images * height * width > (1ll << 28))
+        return fail(SGM_EINVAL, "batch %d x %d x %d outside 1..2^28 pixels", max_images, height, width);
+    sgm_cnn *t = new (std::nothrow) sgm_cnn();
+    if (!t)
+        return fail(SGM_ENOMEM, "host allocation failed");
+    memset(t, 0, sizeof(*t));
+    t->maxn = max_images;
+    t->H = height;
+    t->W = width;
+    if (hipGetDevice(&t->device) != hipSuccess) {
+        delete t;
+        return fail(SGM_EHIP, "no HIP device");
+    }
+    const size_t P = (size_t)max_images * height * width;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t r) {
+        if (e == hipSuccess)
+            e = r;
+    };
+    A(dalloc(&t->theta, (size_t)SGM_CNN_NPARAMS));
+    A(dalloc(&t->m, (size_t)SGM_CNN_NPARAMS));
+    A(dalloc(&t->v, (size_t)SGM_CNN_NPARAMS));
+    A(dalloc(&t->grad, (size_t)SGM_CNN_NPARAMS));
+    A(dalloc(&t->frag, cnn_frag_count()));
+    A(dalloc(&t->a1, P * 16));
+    A(dalloc(&t->a2, P * 32));
+    A(dalloc(&t->a3, P * 32));
+    A(dalloc(&t->a4, P * 16));
+    A(dalloc(&t->g0, P * 32));
+    A(dalloc(&t->g1, P * 32));
+    A(dalloc(&t->dz5, P * 4));
+    A(dalloc(&t->out, P * 2));
+    A(dalloc(&t->cnt, 2));
+    A(dalloc(&t->part, cnn_part_floats()));
+    A(dalloc(&t->lpart, cnn_loss_part_floats()));
+    if (e == hipSuccess) {
+        A(hipMemset(t->theta, 0, SGM_CNN_NPARAMS * sizeof(float)));
+        A(hipMemset(t->m, 0, SGM_CNN_NPARAMS * sizeof(float)));
+        A(hipMemset(t->v, 0, SGM_CNN_NPARAMS * sizeof(float)));
+        A(hipMemset(t->grad, 0, SGM_CNN_NPARAMS * sizeof(float)));
+        A(hipDeviceSynchronize());
+    }
+    if (e != hipSuccess) {
+        cnn_free(t);
+        delete t;
+        return fail(SGM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = t;
+    return SGM_OK;
+}
+
+void sgm_cnn_destroy(sgm_cnn *t)
+{
+    if (!t)
+        return;
+    (void)hipDeviceSynchronize();
+    cnn_free(t);
+    delete t;
+}
+
+int sgm_cnn_set_params(sgm_cnn *t, const float *params, int32_t n)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!params || n != SGM_CNN_NPARAMS)
+        return fail(SGM_EINVAL, "need %d parameters (got %d)", SGM_CNN_NPARAMS, n);
+    hipError_t e = hipMemcpy(t->theta, params, (size_t)n * sizeof(float), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemset(t->m, 0, (size_t)n * sizeof(float));
+    if (e == hipSuccess)
+        e = hipMemset(t->v, 0, (size_t)n * sizeof(float));
+    if (e == hipSuccess)
+        e = cnn_pack(t->theta, t->frag, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (e != hipSuccess)
+        return hip_fail(e, "parameter upload");
+    t->step = 0;
+    return SGM_OK;
+}
+
+int sgm_cnn_get_params(sgm_cnn *t, float *params, int32_t n)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!params || n != SGM_CNN_NPARAMS)
+        return fail(SGM_EINVAL, "need room for %d parameters (got %d)", SGM_CNN_NPARAMS, n);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(params, t->theta, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "parameter read-back");
+}
+
+int sgm_cnn_forward(sgm_cnn *t, const uint16_t *x, int32_t nimg, float *out, void *stream)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!x || nimg < 1 || nimg > t->maxn)
+        return fail(SGM_EINVAL, "need an input and 1 <= nimg <= %d (got %d)", t->maxn, nimg);
+    hipStream_t s = as_stream(stream);
+    hipError_t e = cnn_forward(t->theta, t->frag, x, nimg, t->H, t->W, t->a1, t->a2, t->a3, t->a4, t->out, s);
+    const size_t P = (size_t)nimg * t->H * t->W;
+    if (e == hipSuccess && out)
+        e = hipMemcpyAsync(out, t->out, P * 2 * sizeof(float), hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "network forward");
+    t->x = x;
+    t->nimg = nimg;
+    t->have_loss = false;
+    return SGM_OK;
+}
+
+int sgm_cnn_loss(sgm_cnn *t, const float *targets, float *loss, void *stream)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!targets || !loss)
+        return fail(SGM_EINVAL, "NULL targets or loss");
+    if (t->nimg == 0)
+        return fail(SGM_ESTATE, "loss before forward");
+    const size_t P = (size_t)t->nimg * t->H * t->W;
+    hipError_t e = cnn_loss(t->out, targets, P, t->cnt, t->lpart, t->dz5, loss, as_stream(stream));
+    if (e != hipSuccess)
+        return hip_fail(e, "loss launch");
+    t->have_loss = true;
+    return SGM_OK;
+}
+
+int sgm_cnn_backward(sgm_cnn *t, void *stream)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!t->have_loss)
+        return fail(SGM_ESTATE, "backward before forward and loss");
+    hipError_t e = cnn_backward(t->theta, t->frag, t->x, t->a1, t->a2, t->a3, t->a4, t->dz5, t->nimg, t->H, t->W,
+                                t->g0, t->g1, t->part, t->grad, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "network backward");
+}
+
+int sgm_cnn_get_grads(sgm_cnn *t, float *grads, int32_t n)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!grads || n != SGM_CNN_NPARAMS)
+        return fail(SGM_EINVAL, "need room for %d gradients (got %d)", SGM_CNN_NPARAMS, n);
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(grads, t->grad, (size_t)n * sizeof(float), hipMemcpyDeviceToHost);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "gradient read-back");
+}
+
+int sgm_cnn_adam(sgm_cnn *t, float lr, void *stream)
+{
+    int rc = check_cnn(t);
+    if (rc)
+        return rc;
+    if (!(lr > 0.f) || !isfinite(lr))
+        return fail(SGM_EINVAL, "learning rate must be positive and finite");
+    hipStream_t s = as_stream(stream);
+    hipError_t e = cnn_adam(t->theta, t->m, t->v, t->grad, t->step + 1, lr, s);
+    if (e == hipSuccess)
+        e = cnn_pack(t->theta, t->frag, s);
+    if (e != hipSuccess)
+        return hip_fail(e, "Adam launch");
+    t->step++;
+    return SGM_OK;
+}
+
+int sgm_cnn_train_step(sgm_cnn *t, const uint16_t *x, const float *targets, int32_t nimg, float lr, float *loss,
+                       void *stream)
+{
+    int rc = sgm_cnn_forward(t, x, nimg, nullptr, stream);
+    if (rc == SGM_OK)
+        rc = sgm_cnn_loss(t, targets, loss, stream);
+    if (rc == SGM_OK)
+        rc = sgm_cnn_backward(t, stream);
+    if (rc == SGM_OK)
+        rc = sgm_cnn_adam(t, lr, stream);
+    return rc;
 }
 
 }  // extern "C"

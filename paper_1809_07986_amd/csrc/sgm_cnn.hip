@@ -1,0 +1,672 @@
+// Learned search window: a five-layer 3x3 convolutional network (channels
+// 4 -> 16 -> 32 -> 32 -> 16 -> 2, ReLU between layers) that maps each
+// pixel's prediction to a search half-width and a measurement variance, its
+// training (backward pass, Gaussian NLL loss, Adam) and the per-pixel glue
+// (network input, head, training targets).
+//
+// Convolutions are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x16_bf16, fp32 accumulation): M = 16 output pixels of a
+// row, N = output channels, K = (tap, input channel).  Activations are NHWC
+// bfloat16; weights are pre-arranged ("fragments") so that each lane of a
+// wave loads its four K values of the B operand with one 8-byte read.
+#include "sgm_internal.h"
+
+namespace sgmk {
+
+typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
+typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
+
+constexpr int kCin[kCnnLayers] = {4, 16, 32, 32, 16};
+constexpr int kCout[kCnnLayers] = {16, 32, 32, 16, 2};
+
+__host__ __device__ constexpr int ksteps(int cin) { return (9 * cin + 15) / 16; }
+__host__ __device__ constexpr int ntiles(int cout) { return (cout + 15) / 16; }
+// channel count of a layer's output gradient as stored (multiple of 4)
+__host__ __device__ constexpr int pad4(int c) { return (c + 3) & ~3; }
+
+// offsets of each layer's weights W[co][ky][kx][ci] and biases b[co] in the
+// flat parameter vector
+__host__ __device__ constexpr int param_off(int l)
+{
+    int o = 0;
+    for (int i = 0; i < l; i++)
+        o += 9 * kCin[i] * kCout[i] + kCout[i];
+    return o;
+}
+static_assert(param_off(kCnnLayers) == SGM_CNN_NPARAMS, "parameter count");
+
+// fragments: forward B operand of layer l, then (layers 1..4) the backward
+// (input-gradient) B operand, each [ksteps][ntiles][64 lanes] x 4 bf16
+__host__ __device__ constexpr int ffrag_count(int l) { return ksteps(kCin[l]) * ntiles(kCout[l]) * 64; }
+__host__ __device__ constexpr int bfrag_count(int l) { return ksteps(pad4(kCout[l])) * ntiles(kCin[l]) * 64; }
+__host__ __device__ constexpr int ffrag_total()
+{
+    int o = 0;
+    for (int i = 0; i < kCnnLayers; i++)
+        o += ffrag_count(i);
+    return o;
+}
+// start of layer l's forward (bwd = false) or backward (bwd = true, l >= 1)
+// fragments; frag_off(kCnnLayers, true) is the total
+__host__ __device__ constexpr int frag_off(int l, bool bwd)
+{
+    int o = 0;
+    for (int i = 0; i < kCnnLayers; i++) {
+        if (i == l && !bwd)
+            return o;
+        o += ffrag_count(i);
+    }
+    for (int i = 1; i < kCnnLayers; i++) {
+        if (i == l && bwd)
+            return o;
+        o += bfrag_count(i);
+    }
+    return o;
+}
+
+size_t cnn_frag_count() { return (size_t)frag_off(kCnnLayers, true); }
+
+__device__ __forceinline__ uint16_t f32_to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);   // round to nearest, ties to even (finite inputs)
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// bfloat16 nearest to a double, ties to even, directly from the 52-bit
+// significand (no intermediate float rounding); magnitudes below 2^-126
+// give signed zero
+__device__ __forceinline__ uint16_t f64_to_bf16(double x)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const uint64_t sign = b >> 63;
+    const uint64_t mag = b & 0x7FFFFFFFFFFFFFFFull;
+    const uint64_t r = (mag + ((1ull << 44) - 1) + ((mag >> 45) & 1ull)) >> 45;
+    const int64_t e = (int64_t)(r >> 7) - 1023 + 127;
+    uint64_t bits = 0;
+    if (e >= 1)
+        bits = ((uint64_t)(e > 255 ? 255 : e) << 7) | (r & 0x7F);
+    return (uint16_t)((sign << 15) | bits);
+}
+
+// ---------------------------------------------------------------------------
+// fragment packing (from the fp32 parameter vector)
+// ---------------------------------------------------------------------------
+
+__global__ void k_pack(const float *__restrict__ theta, uint64_t *__restrict__ frag)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int)frag_off(kCnnLayers, true))
+        return;
+    const bool bwd = idx >= ffrag_total();
+    int l = bwd ? 1 : 0;
+    while (l + 1 < kCnnLayers && idx >= frag_off(l + 1, bwd))
+        l++;
+    const int local = idx - frag_off(l, bwd);
+    const int cin = kCin[l], cout = kCout[l];
+    const float *W = theta + param_off(l);
+    // GEMM operand B[k][n] of this direction
+    const int kin = bwd ? pad4(cout) : cin;      // channels of the operand's input
+    const int nout = bwd ? cin : cout;
+    const int nt_count = ntiles(nout);
+    const int lane = local & 63;
+    const int nt = (local >> 6) % nt_count;
+    const int kk = (local >> 6) / nt_count;
+    const int n = nt * 16 + (lane & 15);
+    uint64_t packed = 0;
+    for (int e = 0; e < 4; e++) {
+        const int k = kk * 16 + (lane >> 4) * 4 + e;
+        float v = 0.f;
+        if (k < 9 * kin && n < nout) {
+            const int tap = k / kin, c = k % kin;
+            if (!bwd)
+                v = W[(n * 9 + tap) * cin + c];                       // W[n][tap][c]
+            else if (c < cout)
+                v = W[(c * 9 + (8 - tap)) * cin + n];                 // W[c][flipped tap][n]
+        }
+        packed |= (uint64_t)f32_to_bf16(v) << (16 * e);
+    }
+    frag[idx] = packed;
+}
+
+hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s)
+{
+    const int n = (int)cnn_frag_count();
+    hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, theta, frag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, implicit GEMM on MFMA
+// ---------------------------------------------------------------------------
+
+constexpr int CV_TY = 8, CV_TX = 32;   // output tile of a block (4 waves x 4 M-tiles of 16 px)
+
+enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2 };
+
+// out[p][n] = sum_{tap, c} B[tap*CIN + c][n] * x[p + tap][c]  (zero padding)
+//  EPI_RELU: + bias, ReLU, bfloat16 out [p][COUT]
+//  EPI_F32 : + bias, float out [p][COUT]
+//  EPI_MASK: * (mask[p][n] > 0), bfloat16 out [p][COUT] (input gradient through a ReLU)
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(256) void k_conv(int H, int W, const uint16_t *__restrict__ x,
+                                              const uint64_t *__restrict__ frag, const float *__restrict__ bias,
+                                              const uint16_t *__restrict__ mask, uint16_t *__restrict__ y,
+                                              float *__restrict__ yf)
+{
+    constexpr int KS = ksteps(CIN), NT = ntiles(COUT);
+    constexpr int SY = CV_TY + 2, SX = CV_TX + 2;
+    __shared__ __align__(16) uint16_t tile[SY * SX * CIN];
+    const int img = blockIdx.z;
+    const int y0 = blockIdx.y * CV_TY, x0 = blockIdx.x * CV_TX;
+    const size_t ibase = (size_t)img * H * W;
+    // stage the input tile with its one-pixel halo (zeros outside the image)
+    for (int e = threadIdx.x; e < SY * SX * (CIN / 4); e += 256) {
+        const int q = e % (CIN / 4), px = e / (CIN / 4);
+        const int sy = px / SX, sx = px % SX;
+        const int gy = y0 + sy - 1, gx = x0 + sx - 1;
+        uint2 v = make_uint2(0u, 0u);
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+            v = *(const uint2 *)(x + (ibase + (size_t)gy * W + gx) * CIN + 4 * q);
+        *(uint2 *)(tile + px * CIN + 4 * q) = v;
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane >> 4, col = lane & 15;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int m = 0; m < 4; m++)
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+            acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kk = 0; kk < KS; kk++) {
+        const int k0 = kk * 16 + grp * 4;
+        const int tap = k0 / CIN, c0 = k0 % CIN;
+        const bool kval = k0 < 9 * CIN;
+        const int ky = tap / 3, kx = tap % 3;
+        bf16x4 b[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const uint64_t f = frag[(kk * NT + t) * 64 + lane];
+            b[t] = __builtin_bit_cast(bf16x4, f);
+        }
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const int row = wave * 2 + (m >> 1);
+            const int cx = (m & 1) * 16 + col;
+            uint64_t av = 0;
+            if (kval)
+                av = *(const uint64_t *)(tile + ((row + ky) * SX + cx + kx) * CIN + c0);
+            const bf16x4 a = __builtin_bit_cast(bf16x4, av);
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[m][t], 0, 0, 0);
+        }
+    }
+    // D[i][n]: lane holds rows i = 4*grp + e (pixels) of column n = col (channel)
+#pragma unroll
+    for (int m = 0; m < 4; m++) {
+        const int gy = y0 + wave * 2 + (m >> 1);
+        if (gy >= H)
+            continue;
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int n = t * 16 + col;
+            if (n >= COUT)
+                continue;
+            const float bv = (EPI != EPI_MASK) ? bias[n] : 0.f;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const int gx = x0 + (m & 1) * 16 + grp * 4 + e;
+                if (gx >= W)
+                    continue;
+                const size_t p = ibase + (size_t)gy * W + gx;
+                const float v = acc[m][t][e];
+                if (EPI == EPI_RELU) {
+                    y[p * COUT + n] = f32_to_bf16(fmaxf(v + bv, 0.f));
+                } else if (EPI == EPI_F32) {
+                    yf[p * COUT + n] = v + bv;
+                } else {
+                    const bool pass = (mask[p * COUT + n] & 0x7FFFu) != 0;
+                    y[p * COUT + n] = f32_to_bf16(pass ? v : 0.f);
+                }
+            }
+        }
+    }
+}
+
+template <int CIN, int COUT, int EPI>
+static hipError_t conv(int nimg, int H, int W, const uint16_t *x, const uint64_t *frag, const float *bias,
+                       const uint16_t *mask, uint16_t *y, float *yf, hipStream_t s)
+{
+    dim3 grd((W + CV_TX - 1) / CV_TX, (H + CV_TY - 1) / CV_TY, nimg);
+    hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), grd, dim3(256), 0, s, H, W, x, frag, bias, mask, y, yf);
+    return hipGetLastError();
+}
+
+hipError_t cnn_forward(const float *theta, const uint64_t *frag, const uint16_t *x, int nimg, int H, int W,
+                       uint16_t *a1, uint16_t *a2, uint16_t *a3, uint16_t *a4, float *out, hipStream_t s)
+{
+    hipError_t e;
+#define CNN_TRY(call)                 \
+    do {                              \
+        if ((e = (call)) != hipSuccess) \
+            return e;                 \
+    } while (0)
+    CNN_TRY((conv<4, 16, EPI_RELU>(nimg, H, W, x, frag + frag_off(0, false), theta + param_off(0) + 9 * 4 * 16,
+                                   nullptr, a1, nullptr, s)));
+    CNN_TRY((conv<16, 32, EPI_RELU>(nimg, H, W, a1, frag + frag_off(1, false),
+                                    theta + param_off(1) + 9 * 16 * 32, nullptr, a2, nullptr, s)));
+    CNN_TRY((conv<32, 32, EPI_RELU>(nimg, H, W, a2, frag + frag_off(2, false),
+                                    theta + param_off(2) + 9 * 32 * 32, nullptr, a3, nullptr, s)));
+    CNN_TRY((conv<32, 16, EPI_RELU>(nimg, H, W, a3, frag + frag_off(3, false),
+                                    theta + param_off(3) + 9 * 32 * 16, nullptr, a4, nullptr, s)));
+    CNN_TRY((conv<16, 2, EPI_F32>(nimg, H, W, a4, frag + frag_off(4, false), theta + param_off(4) + 9 * 16 * 2,
+                                  nullptr, nullptr, out, s)));
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// weight gradients: dW[co][tap][ci] = sum_p g[p][co] * x[p + tap][ci],
+// db[co] = sum_p g[p][co]; GEMM with M = co, N = (tap, ci), K = pixels.
+// Each block accumulates over row segments of 64 pixels and writes its
+// partial sums; a second kernel adds the partials in a fixed order.
+// ---------------------------------------------------------------------------
+
+constexpr int WG_SEG = 64;
+constexpr int kWgradBlocks = 240;
+
+template <int CIN, int COUT, int GS>
+__global__ __launch_bounds__(256) void k_wgrad(int nimg, int H, int W, const uint16_t *__restrict__ x,
+                                               const uint16_t *__restrict__ g, float *__restrict__ part)
+{
+    constexpr int MT = ntiles(COUT), NTW = ksteps(CIN);   // (tap, ci) columns in tiles of 16
+    constexpr int NPAIR = MT * NTW, PPW = (NPAIR + 3) / 4;
+    constexpr int SX = WG_SEG + 2;
+    constexpr int NW = 9 * CIN * COUT + COUT;
+    __shared__ __align__(16) uint16_t sx[3 * SX * CIN];
+    __shared__ __align__(16) uint16_t sg[WG_SEG * GS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int grp = lane >> 4, col = lane & 15;
+    f32x4 acc[PPW];
+#pragma unroll
+    for (int q = 0; q < PPW; q++)
+        acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    const int segs = (W + WG_SEG - 1) / WG_SEG;
+    const long ntile = (long)nimg * H * segs;
+    for (long tI = blockIdx.x; tI < ntile; tI += gridDim.x) {
+        const int sgi = (int)(tI % segs);
+        const long rowi = tI / segs;
+        const int yy = (int)(rowi % H), img = (int)(rowi / H);
+        const int x0 = sgi * WG_SEG;
+        const size_t ibase = (size_t)img * H * W;
+        __syncthreads();   // previous tile fully consumed
+        for (int e = threadIdx.x; e < 3 * SX * (CIN / 4); e += 256) {
+            const int q = e % (CIN / 4), px = e / (CIN / 4);
+            const int r = px / SX, c = px % SX;
+            const int gy = yy + r - 1, gx = x0 + c - 1;
+            uint2 v = make_uint2(0u, 0u);
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+                v = *(const uint2 *)(x + (ibase + (size_t)gy * W + gx) * CIN + 4 * q);
+            *(uint2 *)(sx + px * CIN + 4 * q) = v;
+        }
+        for (int e = threadIdx.x; e < WG_SEG * (GS / 4); e += 256) {
+            const int q = e % (GS / 4), px = e / (GS / 4);
+            const int gx = x0 + px;
+            uint2 v = make_uint2(0u, 0u);
+            if (gx < W)
+                v = *(const uint2 *)(g + (ibase + (size_t)yy * W + gx) * GS + 4 * q);
+            *(uint2 *)(sg + px * GS + 4 * q) = v;
+        }
+        __syncthreads();
+        if (threadIdx.x < COUT) {
+            float s = 0.f;
+            for (int px = 0; px < WG_SEG; px++)
+                s += bf16_to_f32(sg[px * GS + threadIdx.x]);
+            bacc += s;
+        }
+#pragma unroll
+        for (int ks = 0; ks < WG_SEG / 16; ks++) {
+            const int pbase = ks * 16 + grp * 4;
+#pragma unroll
+            for (int q = 0; q < PPW; q++) {
+                const int pr = wave + 4 * q;
+                if (pr >= NPAIR)
+                    break;
+                const int mt = pr / NTW, nt = pr % NTW;
+                const int co = mt * 16 + col;
+                const int j = nt * 16 + col;
+                uint16_t av[4], bv[4];
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    av[e] = co < COUT ? sg[(pbase + e) * GS + co] : (uint16_t)0;
+                    uint16_t v = 0;
+                    if (j < 9 * CIN) {
+                        const int tap = j / CIN, ci = j % CIN;
+                        v = sx[((tap / 3) * SX + pbase + e + (tap % 3)) * CIN + ci];
+                    }
+                    bv[e] = v;
+                }
+                const uint64_t ap = (uint64_t)av[0] | ((uint64_t)av[1] << 16) | ((uint64_t)av[2] << 32) |
+                                    ((uint64_t)av[3] << 48);
+                const uint64_t bp = (uint64_t)bv[0] | ((uint64_t)bv[1] << 16) | ((uint64_t)bv[2] << 32) |
+                                    ((uint64_t)bv[3] << 48);
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(bf16x4, ap),
+                                                                    __builtin_bit_cast(bf16x4, bp), acc[q], 0, 0,
+                                                                    0);
+            }
+        }
+    }
+    float *pb = part + (size_t)blockIdx.x * NW;
+#pragma unroll
+    for (int q = 0; q < PPW; q++) {
+        const int pr = wave + 4 * q;
+        if (pr >= NPAIR)
+            break;
+        const int mt = pr / NTW, nt = pr % NTW;
+        const int j = nt * 16 + col;
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const int co = mt * 16 + grp * 4 + e;
+            if (co < COUT && j < 9 * CIN)
+                pb[co * 9 * CIN + j] = acc[q][e];
+        }
+    }
+    if (threadIdx.x < COUT)
+        pb[9 * CIN * COUT + threadIdx.x] = bacc;
+}
+
+__global__ void k_sum_parts(int nblk, int nw, const float *__restrict__ part, float *__restrict__ out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw)
+        return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; b++)
+        s += part[(size_t)b * nw + i];
+    out[i] = s;
+}
+
+size_t cnn_part_floats()
+{
+    size_t m = 0;
+    for (int l = 0; l < kCnnLayers; l++) {
+        size_t nw = (size_t)9 * kCin[l] * kCout[l] + kCout[l];
+        m = nw > m ? nw : m;
+    }
+    return m * kWgradBlocks;
+}
+
+template <int CIN, int COUT, int GS>
+static hipError_t wgrad(int nimg, int H, int W, const uint16_t *x, const uint16_t *g, float *part, float *out,
+                        hipStream_t s)
+{
+    constexpr int NW = 9 * CIN * COUT + COUT;
+    hipLaunchKernelGGL((k_wgrad<CIN, COUT, GS>), dim3(kWgradBlocks), dim3(256), 0, s, nimg, H, W, x, g, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3((NW + 255) / 256), dim3(256), 0, s, kWgradBlocks, NW, part, out);
+    return hipGetLastError();
+}
+
+hipError_t cnn_backward(const float *theta, const uint64_t *frag, const uint16_t *x, const uint16_t *a1,
+                        const uint16_t *a2, const uint16_t *a3, const uint16_t *a4, const uint16_t *dz5, int nimg,
+                        int H, int W, uint16_t *g0, uint16_t *g1, float *part, float *grad, hipStream_t s)
+{
+    (void)theta;
+    hipError_t e;
+    // layer 5 (16 -> 2): its output gradient is stored with 4 channels
+    CNN_TRY((wgrad<16, 2, 4>(nimg, H, W, a4, dz5, part, grad + param_off(4), s)));
+    CNN_TRY((conv<4, 16, EPI_MASK>(nimg, H, W, dz5, frag + frag_off(4, true), nullptr, a4, g0, nullptr, s)));
+    // layer 4 (32 -> 16)
+    CNN_TRY((wgrad<32, 16, 16>(nimg, H, W, a3, g0, part, grad + param_off(3), s)));
+    CNN_TRY((conv<16, 32, EPI_MASK>(nimg, H, W, g0, frag + frag_off(3, true), nullptr, a3, g1, nullptr, s)));
+    // layer 3 (32 -> 32)
+    CNN_TRY((wgrad<32, 32, 32>(nimg, H, W, a2, g1, part, grad + param_off(2), s)));
+    CNN_TRY((conv<32, 32, EPI_MASK>(nimg, H, W, g1, frag + frag_off(2, true), nullptr, a2, g0, nullptr, s)));
+    // layer 2 (16 -> 32)
+    CNN_TRY((wgrad<16, 32, 32>(nimg, H, W, a1, g0, part, grad + param_off(1), s)));
+    CNN_TRY((conv<32, 16, EPI_MASK>(nimg, H, W, g0, frag + frag_off(1, true), nullptr, a1, g1, nullptr, s)));
+    // layer 1 (4 -> 16)
+    CNN_TRY((wgrad<4, 16, 16>(nimg, H, W, x, g1, part, grad + param_off(0), s)));
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// loss: Gaussian NLL of the prediction residual e (channel 0) and the
+// measurement residual m (channel 1), each averaged over its weighted pixels;
+// writes dL/do as bfloat16 with 4 channels (2, 3 zero)
+// ---------------------------------------------------------------------------
+
+constexpr float kOClampLoss = 15.f;
+constexpr int kLossBlocks = 512;
+
+__global__ void k_count(size_t P, const float *__restrict__ tgt, float *__restrict__ part)
+{
+    __shared__ float s0[256], s1[256];
+    float a = 0.f, b = 0.f;
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < P; i += (size_t)gridDim.x * 256) {
+        a += tgt[i * 4 + 2];
+        b += tgt[i * 4 + 3];
+    }
+    s0[threadIdx.x] = a;
+    s1[threadIdx.x] = b;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            s0[threadIdx.x] += s0[threadIdx.x + h];
+            s1[threadIdx.x] += s1[threadIdx.x + h];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// cnt[0..1] = max(1, sum); one thread block
+__global__ void k_count_final(int nblk, const float *__restrict__ part, float *__restrict__ cnt)
+{
+    if (threadIdx.x >= 2)
+        return;
+    float s = 0.f;
+    for (int b = 0; b < nblk; b++)
+        s += part[2 * b + threadIdx.x];
+    cnt[threadIdx.x] = fmaxf(1.f, s);
+}
+
+__global__ void k_loss(size_t P, const float *__restrict__ out, const float *__restrict__ tgt,
+                       const float *__restrict__ cnt, uint16_t *__restrict__ dz, float *__restrict__ part)
+{
+    __shared__ float sl[256];
+    const float ne = cnt[0], nm = cnt[1];
+    float L = 0.f;
+    for (size_t i = blockIdx.x * 256 + threadIdx.x; i < P; i += (size_t)gridDim.x * 256) {
+        const float4 t = *(const float4 *)(tgt + i * 4);
+        uint16_t gq[2];
+        for (int c = 0; c < 2; c++) {
+            const float o = out[i * 2 + c];
+            const float res = c == 0 ? t.x : t.y;
+            const float w = (c == 0 ? t.z : t.w) / (c == 0 ? ne : nm);
+            const float oc = fminf(fmaxf(o, -kOClampLoss), kOClampLoss);
+            const bool inside = o > -kOClampLoss && o < kOClampLoss;
+            const float ex = expf(-oc);
+            const float r2 = res * res;
+            L += w * 0.5f * (oc + r2 * ex);
+            gq[c] = f32_to_bf16(inside ? w * 0.5f * (1.f - r2 * ex) : 0.f);
+        }
+        *(uint2 *)(dz + i * 4) = make_uint2((uint32_t)gq[0] | ((uint32_t)gq[1] << 16), 0u);
+    }
+    sl[threadIdx.x] = L;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            sl[threadIdx.x] += sl[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = sl[0];
+}
+
+hipError_t cnn_loss(const float *out, const float *tgt, size_t P, float *cnt, float *part, uint16_t *dz,
+                    float *loss, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_count, dim3(kLossBlocks), dim3(256), 0, s, P, tgt, part);
+    hipLaunchKernelGGL(k_count_final, dim3(1), dim3(64), 0, s, kLossBlocks, part, cnt);
+    hipLaunchKernelGGL(k_loss, dim3(kLossBlocks), dim3(256), 0, s, P, out, tgt, cnt, dz, part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, kLossBlocks, 1, part, loss);
+    return hipGetLastError();
+}
+
+size_t cnn_loss_part_floats() { return 2 * kLossBlocks; }
+
+// ---------------------------------------------------------------------------
+// Adam (Kingma & Ba, 2015): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+// theta <- theta - lr * (m c1) / (sqrt(v c2) + eps), c1,2 the bias corrections
+// ---------------------------------------------------------------------------
+
+__global__ void k_adam(int n, float *__restrict__ theta, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, float lr, float b1, float b2, float c1, float c2, float eps)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    theta[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+hipError_t cnn_adam(float *theta, float *m, float *v, const float *g, int step, float lr, hipStream_t s)
+{
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 / (1.0 - pow(b1, step))), c2 = (float)(1.0 / (1.0 - pow(b2, step)));
+    hipLaunchKernelGGL(k_adam, dim3((SGM_CNN_NPARAMS + 255) / 256), dim3(256), 0, s, SGM_CNN_NPARAMS, theta, m, v,
+                       g, lr, (float)b1, (float)b2, c1, c2, 1e-8f);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// per-pixel glue of the learned window
+// ---------------------------------------------------------------------------
+
+// network input of a predicted frame (bfloat16 [N][4]):
+//  0: dhat / 64 (0 without prediction), 1: min(p^-, 16) / 4 (4 without),
+//  2: (|I(x+1)-I(x-1)| + |I(y+1)-I(y-1)|) / 256, neighbours clamped,
+//  3: min(|nu_w|, 8) / 4, nu_w the previous innovation of the warp winner
+__global__ void k_features(int W, int H, const uint8_t *__restrict__ left, int pitch,
+                           const uint8_t *__restrict__ flags, const double *__restrict__ dhat,
+                           const double *__restrict__ pm, const double *__restrict__ nu_w,
+                           uint16_t *__restrict__ feat)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= W * H)
+        return;
+    const int y = t / W, x = t - y * W;
+    const bool pred = flags[t] & SGM_FLAG_PRED;
+    const uint8_t *row = left + (size_t)y * pitch;
+    const int gx = abs((int)row[min(x + 1, W - 1)] - (int)row[max(x - 1, 0)]);
+    const int gy = abs((int)left[(size_t)min(y + 1, H - 1) * pitch + x] - (int)left[(size_t)max(y - 1, 0) * pitch + x]);
+    const double f0 = pred ? dhat[t] * (1.0 / 64.0) : 0.0;
+    const double f1 = pred ? fmin(pm[t], 16.0) * 0.25 : 4.0;
+    const double f2 = (double)(gx + gy) * (1.0 / 256.0);
+    const double f3 = fmin(fabs(nu_w[t]), 8.0) * 0.25;
+    const uint32_t lo = (uint32_t)f64_to_bf16(f0) | ((uint32_t)f64_to_bf16(f1) << 16);
+    const uint32_t hi = (uint32_t)f64_to_bf16(f2) | ((uint32_t)f64_to_bf16(f3) << 16);
+    *(uint2 *)(feat + (size_t)t * 4) = make_uint2(lo, hi);
+}
+
+hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t *left, int pitch, uint16_t *feat,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_features, dim3((g.N + 255) / 256), dim3(256), 0, s, g.W, g.H, left, pitch, b.flags, b.dhat,
+                       b.pm, b.nu_w, feat);
+    return hipGetLastError();
+}
+
+// network output -> half-width w = max(1, k exp(o0 / 2)) and measurement
+// variance r = clamp(exp(o1), 1/16, 64) (o clipped to +-30); pixels with a
+// finite window get [floor(dhat - w), ceil(dhat + w)] (double precision),
+// or the full range when w >= 32
+__global__ void k_head(int N, int D, float k_sigma, const float *__restrict__ out, const double *__restrict__ dhat,
+                       float *__restrict__ hw, float *__restrict__ rpix, uint8_t *__restrict__ flags,
+                       uint16_t *__restrict__ win)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N)
+        return;
+    const float o0 = fminf(fmaxf(out[2 * t], -30.f), 30.f);
+    const float o1 = fminf(fmaxf(out[2 * t + 1], -30.f), 30.f);
+    const float w = fmaxf(1.f, k_sigma * expf(0.5f * o0));
+    const float r = fminf(fmaxf(expf(o1), 1.f / 16.f), 64.f);
+    hw[t] = w;
+    rpix[t] = r;
+    const uint8_t fl = flags[t];
+    if (fl & SGM_FLAG_FULLWIN)
+        return;
+    if (!(w < (float)SGM_LEARNED_WMAX)) {
+        flags[t] = fl | SGM_FLAG_FULLWIN;
+        win[t] = (uint16_t)((D - 1) << 8);
+        return;
+    }
+    const double dv = dhat[t];
+    int l = (int)floor(dv - (double)w), h = (int)ceil(dv + (double)w);
+    l = l < 0 ? 0 : l;
+    h = h > D - 1 ? D - 1 : h;
+    win[t] = (uint16_t)(l | ((h - l) << 8));
+}
+
+hipError_t launch_head(const Geometry &g, DevBuffers &b, float k_sigma, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_head, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.D, k_sigma, b.cnn_out, b.dhat,
+                       b.hw, b.rpix, b.flags, b.win);
+    return hipGetLastError();
+}
+
+// pixels that failed the innovation test of the first pass search the full
+// range in the second (FULLWIN | GATEFAIL)
+__global__ void k_gate_widen(int N, int D, const uint8_t *__restrict__ mask, uint8_t *__restrict__ flags,
+                             uint16_t *__restrict__ win)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N || !mask[t])
+        return;
+    flags[t] |= SGM_FLAG_FULLWIN | SGM_FLAG_GATEFAIL;
+    win[t] = (uint16_t)((D - 1) << 8);
+}
+
+hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gate_widen, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.D, b.mask, b.flags, b.win);
+    return hipGetLastError();
+}
+
+// training targets of a predicted frame: e = dz_full - dhat, m = dz_full - gt
+// (clipped to +-16), weights we = [prediction], wm = we * [gt >= 0]
+__global__ void k_targets(int N, const uint8_t *__restrict__ flags, const double *__restrict__ dhat,
+                          const double *__restrict__ dz_full, const float *__restrict__ gt, float *__restrict__ tgt)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N)
+        return;
+    const bool pred = flags[t] & SGM_FLAG_PRED;
+    const bool gv = pred && gt[t] >= 0.f;
+    const double e = fmin(fmax(dz_full[t] - dhat[t], -16.0), 16.0);
+    const double m = fmin(fmax(dz_full[t] - (double)gt[t], -16.0), 16.0);
+    *(float4 *)(tgt + (size_t)t * 4) =
+        make_float4(pred ? (float)e : 0.f, gv ? (float)m : 0.f, pred ? 1.f : 0.f, gv ? 1.f : 0.f);
+}
+
+hipError_t launch_targets(const Geometry &g, const DevBuffers &b, const double *dz_full, const float *gt, float *tgt,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_targets, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, b.flags, b.dhat, dz_full, gt, tgt);
+    return hipGetLastError();
+}
+
+}  // namespace sgmk

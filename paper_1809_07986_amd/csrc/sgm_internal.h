@@ -11,6 +11,7 @@ namespace sgmk {
 
 constexpr int kMaxDisp = 256;          // windows are packed as (lo, width-1) bytes
 constexpr int kMaxPaths = 8;
+constexpr int kCnnLayers = 5;          // learned window network
 
 // Device-side layout of one context.  Per-pixel arrays have N = W*H
 // entries in raster order; cost-volume arrays have N*D entries (the worst
@@ -37,6 +38,15 @@ struct DevBuffers {
     uint8_t *has, *rw, *pred, *rst;
     double *dw, *pw, *dfill, *pfill;
     uint32_t *status;
+    // learned window (allocated in learned mode only, except nu / nu_w)
+    double *nu;                // innovation of the last frame (0 without prediction)
+    double *nu_w;              // previous innovation of each pixel's warp winner
+    uint16_t *feat;            // network input, bfloat16 [N][4]
+    uint16_t *act_a, *act_b;   // activations, bfloat16 [N][32] each
+    float *cnn_out;            // network output [N][2]
+    float *hw, *rpix;          // half-width and measurement variance per pixel
+    float *theta;              // network parameters (fp32)
+    uint64_t *frag;            // bfloat16 MFMA operands of the parameters
 };
 
 struct Geometry {
@@ -73,9 +83,34 @@ hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
 int count_horizontal_paths(const Geometry &g);
 hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s);
 hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s);
-// mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only
+// mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only;
+// rpix: per-pixel measurement variance (NULL: cc.r)
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, hipStream_t s);
+                              bool debug_sum, const float *rpix, hipStream_t s);
+// prediction without the offset scan (launch_predict = this + launch_scan)
+hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
+                               const CorrectConst &cc, hipStream_t s);
+hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s);
+
+// learned window (sgm_cnn.hip)
+size_t cnn_frag_count();
+size_t cnn_part_floats();
+size_t cnn_loss_part_floats();
+hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s);
+hipError_t cnn_forward(const float *theta, const uint64_t *frag, const uint16_t *x, int nimg, int H, int W,
+                       uint16_t *a1, uint16_t *a2, uint16_t *a3, uint16_t *a4, float *out, hipStream_t s);
+hipError_t cnn_backward(const float *theta, const uint64_t *frag, const uint16_t *x, const uint16_t *a1,
+                        const uint16_t *a2, const uint16_t *a3, const uint16_t *a4, const uint16_t *dz5, int nimg,
+                        int H, int W, uint16_t *g0, uint16_t *g1, float *part, float *grad, hipStream_t s);
+hipError_t cnn_loss(const float *out, const float *tgt, size_t P, float *cnt, float *part, uint16_t *dz,
+                    float *loss, hipStream_t s);
+hipError_t cnn_adam(float *theta, float *m, float *v, const float *g, int step, float lr, hipStream_t s);
+hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t *left, int pitch, uint16_t *feat,
+                           hipStream_t s);
+hipError_t launch_head(const Geometry &g, DevBuffers &b, float k_sigma, hipStream_t s);
+hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_targets(const Geometry &g, const DevBuffers &b, const double *dz_full, const float *gt, float *tgt,
+                          hipStream_t s);
 hipError_t launch_windows_to_lohi(const Geometry &g, const DevBuffers &b, int32_t *out, int which,
                                   hipStream_t s);
 hipError_t launch_state_to_f32(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);

@@ -272,8 +272,9 @@ __global__ void k_splat_ties(int N, const int32_t *__restrict__ tgt, const doubl
 // gather the winner; re-arm the z-buffer for the next frame
 __global__ void k_splat_resolve(int N, unsigned long long *__restrict__ zkey, uint32_t *__restrict__ zidx,
                                 const double *__restrict__ dprime, const double *__restrict__ pprime,
-                                const uint8_t *__restrict__ sflags, uint8_t *__restrict__ has,
-                                double *__restrict__ dw, double *__restrict__ pw, uint8_t *__restrict__ rw)
+                                const uint8_t *__restrict__ sflags, const double *__restrict__ nu,
+                                uint8_t *__restrict__ has, double *__restrict__ dw, double *__restrict__ pw,
+                                uint8_t *__restrict__ rw, double *__restrict__ nu_w)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= N)
@@ -284,11 +285,13 @@ __global__ void k_splat_resolve(int N, unsigned long long *__restrict__ zkey, ui
         dw[t] = dprime[w];
         pw[t] = pprime[w];
         rw[t] = sflags[w] & SGM_FLAG_RESET;
+        nu_w[t] = nu[w];
     } else {
         has[t] = 0;
         dw[t] = 0.0;
         pw[t] = 0.0;
         rw[t] = 0;
+        nu_w[t] = 0.0;
     }
     zkey[t] = 0ull;
     zidx[t] = 0xFFFFFFFFu;
@@ -339,7 +342,8 @@ __global__ void k_fill(int W, int H, const uint8_t *__restrict__ has, const doub
 __global__ void k_disc_windows(int W, int H, int D, CorrectConst cc, const uint8_t *__restrict__ pred,
                                const double *__restrict__ dfill, const double *__restrict__ pfill,
                                const uint8_t *__restrict__ rst, uint8_t *__restrict__ flags,
-                               uint16_t *__restrict__ win, double *__restrict__ dhat, double *__restrict__ pm)
+                               uint16_t *__restrict__ win, double *__restrict__ dhat, double *__restrict__ pm,
+                               double *__restrict__ nu_w)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= W * H)
@@ -380,24 +384,32 @@ __global__ void k_disc_windows(int W, int H, int D, CorrectConst cc, const uint8
     flags[t] = fl;
     dhat[t] = ok ? dv : 0.0;
     pm[t] = ok ? pv : 0.0;
+    if (!ok)
+        nu_w[t] = 0.0;
 }
 
 hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
                           const CorrectConst &cc, hipStream_t s)
 {
+    hipError_t e = launch_predict_core(g, b, wc, Tdev, cc, s);
+    if (e != hipSuccess)
+        return e;
+    return launch_scan(g, b, s);
+}
+
+hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
+                               const CorrectConst &cc, hipStream_t s)
+{
     dim3 blk(256), grd((g.N + 255) / 256);
     hipLaunchKernelGGL(k_splat, grd, blk, 0, s, g.W, g.H, g.D, wc, Tdev, b.d, b.p, b.tgt, b.dprime, b.pprime,
                        b.zkey);
     hipLaunchKernelGGL(k_splat_ties, grd, blk, 0, s, g.N, b.tgt, b.dprime, b.zkey, b.zidx);
-    hipLaunchKernelGGL(k_splat_resolve, grd, blk, 0, s, g.N, b.zkey, b.zidx, b.dprime, b.pprime, b.sflags, b.has,
-                       b.dw, b.pw, b.rw);
+    hipLaunchKernelGGL(k_splat_resolve, grd, blk, 0, s, g.N, b.zkey, b.zidx, b.dprime, b.pprime, b.sflags, b.nu,
+                       b.has, b.dw, b.pw, b.rw, b.nu_w);
     hipLaunchKernelGGL(k_fill, grd, blk, 0, s, g.W, g.H, b.has, b.dw, b.pw, b.rw, b.pred, b.dfill, b.pfill, b.rst);
     hipLaunchKernelGGL(k_disc_windows, grd, blk, 0, s, g.W, g.H, g.D, cc, b.pred, b.dfill, b.pfill, b.rst, b.flags,
-                       b.win, b.dhat, b.pm);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        return e;
-    return launch_scan(g, b, s);
+                       b.win, b.dhat, b.pm, b.nu_w);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -1097,7 +1109,8 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        const double *__restrict__ pm, uint16_t *__restrict__ dbg_sum,
                                                        int32_t *__restrict__ dstar_out, double *__restrict__ dz_out,
                                                        double *__restrict__ d_state, double *__restrict__ p_state,
-                                                       uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags)
+                                                       uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags,
+                                                       const float *__restrict__ rpix, double *__restrict__ nu_out)
 {
     __shared__ uint16_t ssum[WTA_NG][kMaxDisp + 8];
     const int grp = threadIdx.x / WTA_G, lane = threadIdx.x % WTA_G;
@@ -1152,13 +1165,24 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     if (mode == 2)
         return;
     const uint8_t fl = flags[t];
+    const double r = rpix ? (double)rpix[t] : cc.r;
     bool moving = false;
     double nu = 0.0, S = 0.0;
     const double dh = dhat[t], pv = pm[t];
     if (fl & SGM_FLAG_PRED) {
         nu = dz - dh;
-        S = pv + cc.r;
+        S = pv + r;
         moving = (nu * nu) / S > cc.gate;
+    }
+    nu_out[t] = nu;
+    if (fl & SGM_FLAG_GATEFAIL) {
+        // failed the first pass's innovation test and re-measured over the
+        // full range: restart from that measurement, stays marked moving
+        d_state[t] = dz;
+        p_state[t] = cc.r;
+        mask[t] = 1;
+        sflags[t] = SGM_FLAG_RESET;
+        return;
     }
     if (fl & SGM_FLAG_FULLWIN) {
         d_state[t] = dz;
@@ -1167,7 +1191,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
         const double K = pv / S;
         const double am = 1.0 - K;
         d_state[t] = dh + K * nu;
-        p_state[t] = (am * am) * pv + (K * K) * cc.r;
+        p_state[t] = (am * am) * pv + (K * K) * r;
     }
     const bool sat = (ds == lo && lo > 0) || (ds == hi && hi < D - 1);
     mask[t] = moving ? 1 : 0;
@@ -1175,11 +1199,12 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
 }
 
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, hipStream_t s)
+                              bool debug_sum, const float *rpix, hipStream_t s)
 {
     hipLaunchKernelGGL(k_wta_correct, dim3((g.N + WTA_NG - 1) / WTA_NG), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
-                       debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags);
+                       debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
+                       b.nu);
     return hipGetLastError();
 }
 
