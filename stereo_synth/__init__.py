@@ -238,7 +238,7 @@ def _scene_tiny(K: int, rng: np.random.Generator):
 
 
 def _scene_driving(K: int, speed: float, rng: np.random.Generator, n_cars: int = 4, cam_h: float = 1.65,
-                   depth: float = 120.0, cs=None):
+                   depth: float = 120.0, cs=None, near: Optional[float] = None):
     prims = []
     ex = np.array([1.0, 0.0, 0.0])
     ey = np.array([0.0, 1.0, 0.0])
@@ -261,13 +261,18 @@ def _scene_driving(K: int, speed: float, rng: np.random.Generator, n_cars: int =
             prims.append(bx)
             z += length + rng.uniform(2.0, 8.0)
     # cars: independent (x, z, yaw) motion, kept >= 6 m from the ego centre
+    # (with `near`, the nearest car surface may come to about `near` metres)
+    min_dist = 6.0 if near is None else near + 2.1
     lanes = [-3.5, 0.0, 3.5, -3.5, 3.5, 0.0, -7.0, 7.0]
     placed = 0
     tries = 0
     while placed < n_cars and tries < 1000:
         tries += 1
         lane = lanes[placed % len(lanes)] + rng.uniform(-0.4, 0.4)
-        z0 = rng.uniform(12.0, 45.0) + 6.0 * placed
+        if near is None:
+            z0 = rng.uniform(12.0, 45.0) + 6.0 * placed
+        else:
+            z0 = rng.uniform(min_dist, 25.0) + 4.0 * placed
         v = rng.uniform(0.5, 2.0) * (1.0 if lane >= 0 else -1.0)
         yaw = rng.uniform(-0.1, 0.1)
         centers, yaws = [], []
@@ -283,7 +288,7 @@ def _scene_driving(K: int, speed: float, rng: np.random.Generator, n_cars: int =
         centers = np.array(centers)
         ok = True
         for k in range(K):
-            if np.linalg.norm(centers[k] - cs[k] - np.array([0, cam_h - 0.75, 0])) < 6.0:
+            if np.linalg.norm(centers[k] - cs[k] - np.array([0, cam_h - 0.75, 0])) < min_dist:
                 ok = False
         for other in prims:
             if isinstance(other, _Box) and other.mover:
@@ -299,8 +304,9 @@ def _scene_driving(K: int, speed: float, rng: np.random.Generator, n_cars: int =
     return prims
 
 
-def _scene_movers(K: int, speed: float, rng: np.random.Generator, n_movers: int, cam_h: float, cs):
-    prims = _scene_driving(K, speed, rng, n_cars=n_movers, cam_h=cam_h, depth=40.0 + speed * K, cs=cs)
+def _scene_movers(K: int, speed: float, rng: np.random.Generator, n_movers: int, cam_h: float, cs,
+                  near: Optional[float] = None):
+    prims = _scene_driving(K, speed, rng, n_cars=n_movers, cam_h=cam_h, depth=40.0 + speed * K, cs=cs, near=near)
     return prims
 
 
@@ -412,11 +418,15 @@ CONFIGS = {
     # 1242x375, D=128, f=720, B=0.54, 20 frames, 1 m/frame + yaw <= 2 deg, ground, buildings, 4 cars
     "driving": dict(width=1242, height=375, max_disp=128, f=720.0, baseline=0.54, frames=20, speed=1.0,
                     yaw=2.0, noise=2.0, scene="driving", seed=2, cars=4),
+    # learned-window sequences: 1242x375, D=256, 50 frames, 6 cars that may come as near as 1.6 m
+    # (training seeds 4000-4039, held out 4100-4104)
+    "learned": dict(width=1242, height=375, max_disp=256, f=720.0, baseline=0.54, frames=50, speed=1.0,
+                    yaw=2.0, noise=2.0, scene="driving", seed=4000, cars=6, near=1.6),
 }
 
 
 def make_sequence(name: str = "tiny", frames: Optional[int] = None, seed: Optional[int] = None,
-                  cache_dir: Optional[str] = None, **over) -> Sequence:
+                  cache_dir: Optional[str] = None, cache: bool = True, **over) -> Sequence:
     """Render a seeded synthetic stereo sequence.
 
     `name` selects a preset in CONFIGS; keyword overrides change any preset
@@ -436,7 +446,7 @@ def make_sequence(name: str = "tiny", frames: Optional[int] = None, seed: Option
             os.path.abspath(__file__))), "_data"))
     path = os.path.join(cache_dir, f"{name}_{tag}.npz")
     cam = Camera(cfg["width"], cfg["height"], cfg["f"], cfg["baseline"])
-    if os.path.exists(path):
+    if cache and os.path.exists(path):
         z = np.load(path, allow_pickle=False)
         return Sequence(name, cam, cfg["max_disp"], z["left"], z["right"], z["disp_gt"], z["valid"],
                         z["mover"], z["T"])
@@ -446,7 +456,7 @@ def make_sequence(name: str = "tiny", frames: Optional[int] = None, seed: Option
     if cfg["scene"] == "tiny":
         prims = _scene_tiny(K, rng)
     else:
-        prims = _scene_movers(K, cfg["speed"], rng, cfg.get("cars", 4), 1.65, cs)
+        prims = _scene_movers(K, cfg["speed"], rng, cfg.get("cars", 4), 1.65, cs, cfg.get("near"))
     T = _relative_T(cs, Rs)
     D = cfg["max_disp"]
     L, R, G, V, M = [], [], [], [], []
@@ -455,6 +465,8 @@ def make_sequence(name: str = "tiny", frames: Optional[int] = None, seed: Option
         l, r, d, v = _stereo_pair(Z, tex, cam, D, rng, cfg["noise"])
         L.append(l), R.append(r), G.append(d), V.append(v), M.append(mov)
     seq = Sequence(name, cam, D, np.stack(L), np.stack(R), np.stack(G), np.stack(V), np.stack(M), T)
+    if not cache:
+        return seq
     try:
         os.makedirs(cache_dir, exist_ok=True)
         tmp = path + f".tmp{os.getpid()}.npz"

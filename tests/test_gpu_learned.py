@@ -292,3 +292,48 @@ def test_learned_context_needs_a_model():
     assert ei.value.code == NAT.SGM_EINVAL
     with pytest.raises(sgmk.SgmError):
         g.set_window_model(np.zeros(10, np.float32))
+
+
+# ---------------------------------------------------------------- trained network
+
+def _run_variant(seq, theta=None, **kw):
+    g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline, **kw)
+    if theta is not None:
+        g.set_window_model(theta)
+    g.full_frame(seq.left[0], seq.right[0])
+    cells = bad = valid = 0.0
+    for k in range(1, seq.frames):
+        g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).cuda()
+        ok = torch.from_numpy(seq.valid[k]).cuda()
+        cells += g.cost_cells()
+        bad += float(((g.disparity() - gt).abs() > 3)[ok].sum())
+        valid += float(ok.sum())
+    return cells / (seq.frames - 1), bad / valid
+
+
+def test_trained_window_beats_k_sigma_on_a_held_out_sequence():
+    """The shipped network (trained on seeds 4000-4039) against the k-sigma
+    rule on held-out seed 4104: fewer matched cells than k = 8 and fewer bad
+    pixels than k = 3 and k = 8; within 1 percentage point of full range."""
+    _say("trained window vs k-sigma, learned seed 4104, 16 frames")
+    seq = synth.make_sequence("learned", frames=16, seed=4104)
+    theta = sgmk.load_window_model()
+    c3, b3 = _run_variant(seq)
+    c8, b8 = _run_variant(seq, k_sigma=8.0)
+    cl, bl = _run_variant(seq, theta, window_mode=NAT.WIN_LEARNED)
+    g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    bad = valid = 0.0
+    for k in range(1, seq.frames):
+        g.full_frame(seq.left[k], seq.right[k])
+        gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).cuda()
+        ok = torch.from_numpy(seq.valid[k]).cuda()
+        bad += float(((g.disparity() - gt).abs() > 3)[ok].sum())
+        valid += float(ok.sum())
+    bf = bad / valid
+    _say(f"  k=3: {c3 / 1e6:.2f} M cells, {b3:.4%}; k=8: {c8 / 1e6:.2f} M, {b8:.4%}; "
+         f"learned: {cl / 1e6:.2f} M, {bl:.4%}; full: {seq.cam.width * seq.cam.height * seq.max_disp / 1e6:.1f} M, "
+         f"{bf:.4%}")
+    assert cl < c8
+    assert bl < b3 and bl < b8
+    assert bl <= bf + 0.01
