@@ -28,6 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFLOPS = 2500.0     # dense bf16 matrix-core peak of MI355X
+CNN_FLOPS_PER_PIXEL = 38592        # 2 * 9 * (4*16 + 16*32 + 32*32 + 32*16 + 16*2)
 METRIC = "frames/s and cost-cells/s, reduced vs full SGM at 1242×375×128, 1 GPU"
 # Algorithmic bytes per launch ("Roofline"):
 #  aggregation, per path: read left+right census (16 B), window (2 B) and
@@ -123,8 +125,11 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-full", action="store_true", help="skip the full-range comparison (profiling runs)")
-    ap.add_argument("--workload", choices=("driving", "batched"), default="driving",
-                    help="driving: one 1242x375x128 stream (the headline); batched: 16 uneven streams")
+    ap.add_argument("--workload", choices=("driving", "batched", "learned"), default="driving",
+                    help="driving: one 1242x375x128 stream (the headline); batched: 16 uneven streams; "
+                         "learned: learned vs k-sigma windows at 1242x375x256")
+    ap.add_argument("--no-learned", action="store_true", help="omit the learned-window section")
+    ap.add_argument("--learned-steps", type=int, default=200)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -139,6 +144,16 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "learned":
+        res = bench_learned(args)
+        out = {"metric": "frames/s and cost-cells/s, learned vs k-sigma windows at 1242×375×256, 1 GPU",
+               "value": res["learned"]["frames_per_s"], "unit": "frames/s", "n_gpus": 1,
+               "steps": args.learned_steps, "warmup": 20,
+               "ms_per_step": res["learned"]["ms_per_frame"], "higher_is_better": True, "scaling": "weak",
+               "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+               "config": {"workload": res["workload"]}, "learned": res, "roofline": res["roofline_cnn"]}
+        print(json.dumps(out), flush=True)
+        return
     seq = make_sequence("driving")
     H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
     dev = torch.device("cuda", 0)
@@ -280,10 +295,103 @@ def main():
                        "full_range": full["bad_px_gt3"] if full else None, "frames": "1-19"},
         "roofline": roofline,
     }
+    if not args.no_learned:
+        out["learned_window"] = bench_learned(args)
     if not args.no_cpu:
         cb = cpu_baseline(seq, args.cpu_frames)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(out), flush=True)
+
+
+def bench_learned(args):
+    """Learned search window vs the k-sigma rule on a held-out learned
+    sequence (seed 4100, 1242x375, disparities 0..255, 20 frames visited
+    1..19..1): frames/s, matched cells and bad pixels of k-sigma windows,
+    learned windows, learned windows with the gate re-run, and full-range
+    matching; the network stage's matrix-core roofline."""
+    import torch
+    import paper_1809_07986_amd as sgmk
+    from stereo_synth import make_sequence
+
+    seq = make_sequence("learned", frames=20, seed=4100)
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    dev = torch.device("cuda", 0)
+    Ls = torch.from_numpy(seq.left).to(dev)
+    Rs = torch.from_numpy(seq.right).to(dev)
+    theta = sgmk.load_window_model()
+    warm, steps = 20, args.learned_steps
+    sched = frame_schedule(seq.frames, warm + steps)
+    Ts = [sgmk.as_matrix(T_between(seq, a, b)) for a, b in sched]
+    gts = [torch.from_numpy(seq.disp_gt[k].astype(np.float32)).to(dev) for k in range(seq.frames)]
+    vals = [torch.from_numpy(seq.valid[k]).to(dev) for k in range(seq.frames)]
+
+    def make(kw):
+        g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, **kw)
+        if kw.get("window_mode") == sgmk.N.WIN_LEARNED:
+            g.set_window_model(theta)
+        g.full_frame(Ls[0], Rs[0])
+        return g
+
+    res = {"workload": "learned sequence seed 4100 (held out), 1242x375, disparities 0-255, census 9x7, "
+                       "8 paths, frames 1..19..1"}
+    variants = {"ksigma": {}, "learned": {"window_mode": sgmk.N.WIN_LEARNED},
+                "learned_rerun": {"window_mode": sgmk.N.WIN_LEARNED, "gate_rerun": 1}}
+    for name, kw in variants.items():
+        g = make(kw)
+        cells, bad, nval = 0, 0, 0
+        for k in range(1, seq.frames):
+            g.reduced_frame(Ls[k], Rs[k], seq.T[k])
+            cells += g.cost_cells()
+            bad += int(((g.disparity() - gts[k]).abs() > 3)[vals[k]].sum())
+            nval += int(vals[k].sum())
+        g.close()
+        g = make(kw)
+        for i in range(warm):
+            g.reduced_frame(Ls[sched[i][1]], Rs[sched[i][1]], Ts[i])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(warm, warm + steps):
+            g.reduced_frame(Ls[sched[i][1]], Rs[sched[i][1]], Ts[i])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        g.set_profiling(True)
+        for i in range(warm, warm + steps):
+            g.reduced_frame(Ls[sched[i][1]], Rs[sched[i][1]], Ts[i])
+        prof, nprof = g.read_profile()
+        g.close()
+        res[name] = {"frames_per_s": round(steps / dt, 2), "ms_per_frame": round(dt / steps * 1e3, 4),
+                     "cells_per_frame": round(cells / (seq.frames - 1), 1),
+                     "bad_px_gt3": round(bad / max(nval, 1), 6),
+                     "stage_ms": {k: round(v / max(nprof, 1), 5) for k, v in prof.items()}}
+    gf = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline)
+    for k in range(3):
+        gf.full_frame(Ls[k], Rs[k])
+    torch.cuda.synchronize()
+    nfull = max(steps // 4, 10)
+    t0 = time.perf_counter()
+    for i in range(nfull):
+        gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
+    torch.cuda.synchronize()
+    dtf = time.perf_counter() - t0
+    bad, nval = 0, 0
+    for k in range(1, seq.frames):
+        gf.full_frame(Ls[k], Rs[k])
+        bad += int(((gf.disparity() - gts[k]).abs() > 3)[vals[k]].sum())
+        nval += int(vals[k].sum())
+    gf.close()
+    res["full_range"] = {"frames_per_s": round(nfull / dtf, 2), "ms_per_frame": round(dtf / nfull * 1e3, 4),
+                         "cells_per_frame": H * W * D, "bad_px_gt3": round(bad / max(nval, 1), 6)}
+    for name in variants:
+        res[name]["speedup_vs_full"] = round(res[name]["frames_per_s"] / res["full_range"]["frames_per_s"], 3)
+        res[name]["bad_px_increase_vs_full"] = round(res[name]["bad_px_gt3"] - res["full_range"]["bad_px_gt3"], 6)
+    cnn_ms = res["learned"]["stage_ms"]["cnn"]
+    flops = CNN_FLOPS_PER_PIXEL * H * W
+    ach = flops / (cnn_ms * 1e-3) / 1e12
+    res["roofline_cnn"] = {"bound": "mfma", "kernel": "window network (input, 5 conv3x3 MFMA layers, head)",
+                           "achieved": round(ach, 2), "peak": MFMA_BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                           "frac": round(ach / MFMA_BF16_PEAK_TFLOPS, 5), "traffic": None,
+                           "algorithmic_flops_per_launch": flops, "avg_launch_ms": cnn_ms}
+    return res
 
 
 BATCH_STREAMS = ([dict(width=640, height=480, max_disp=64)] * 4 + [dict(width=1242, height=375, max_disp=128)] * 8
