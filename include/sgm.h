@@ -162,6 +162,12 @@ enum {
 };
 int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream);
 int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
+/* Debug switches for the following frames (bit mask, 0 = off):
+ *   SGM_DEBUG_STAGES  record the cost and sum stages (slower);
+ *   SGM_DEBUG_SHORT_SEGMENTS  cut horizontal scanlines into 48-pixel segments
+ *     instead of 160 (results are identical; exercises the segment fix-up). */
+#define SGM_DEBUG_STAGES 1
+#define SGM_DEBUG_SHORT_SEGMENTS 2
 int sgm_set_debug(sgm_context *ctx, int32_t on);
 
 /* Per-stage GPU time, for benchmarks.  While profiling is on, every frame

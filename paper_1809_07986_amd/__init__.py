@@ -159,8 +159,10 @@ class ReducedSGM:
         _check(_lib().sgm_set_state(self._h, _ptr(d), _ptr(p), _ptr(f), _stream()))
         self._keep = (d, p, f)
 
-    def set_debug(self, on: bool = True):
-        _check(_lib().sgm_set_debug(self._h, 1 if on else 0))
+    def set_debug(self, on=True):
+        """True/False: record the cost and sum stages; an int: the SGM_DEBUG_* bit mask."""
+        flags = int(on) if not isinstance(on, bool) else (N.DEBUG_STAGES if on else 0)
+        _check(_lib().sgm_set_debug(self._h, flags))
 
     def set_profiling(self, on: bool = True):
         _check(_lib().sgm_set_profiling(self._h, 1 if on else 0))

@@ -101,7 +101,7 @@ void free_buffers(DevBuffers &b)
     void *all[] = {b.cen_l, b.cen_r, b.win,    b.off,    b.scan_part, b.cost,  b.lr,   b.sum,  b.d,   b.p,
                    b.sflags, b.mask, b.dhat,   b.pm,     b.flags,     b.dstar, b.dz,   b.zkey, b.zidx, b.tgt,
                    b.dprime, b.pprime, b.has, b.rw,     b.pred,      b.rst,   b.dw,   b.pw,   b.dfill, b.pfill,
-                   b.status, b.nu,   b.nu_w,   b.feat,   b.act_a,     b.act_b, b.cnn_out, b.hw, b.rpix, b.theta,
+                   b.status, b.hflag, b.nu,   b.nu_w,   b.feat,   b.act_a,     b.act_b, b.cnn_out, b.hw, b.rpix, b.theta,
                    b.frag};
     for (void *p : all)
         if (p)
@@ -380,6 +380,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     g.D = prm->max_disp;
     g.N = g.W * g.H;
     g.lr_stride = (((size_t)g.N * g.D) + 255) & ~(size_t)255;
+    g.hseg = 160;
     g.cw = prm->census_w;
     g.ch = prm->census_h;
     g.nbits = g.cw * g.ch - 1;
@@ -431,6 +432,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.dfill, N));
     A(dalloc(&b.pfill, N));
     A(dalloc(&b.status, 4));
+    A(dalloc(&b.hflag, (size_t)2 * g.H * kHMaxSeg));
     A(dalloc(&b.nu, N));
     A(dalloc(&b.nu_w, N));
     if (prm->window_mode == SGM_WIN_LEARNED) {
@@ -461,6 +463,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(hipMemset(b.off, 0, (N + 1) * sizeof(uint32_t)));
     A(hipMemset(b.status, 0, sizeof(uint32_t)));
     A(hipMemset(b.nu, 0, N * sizeof(double)));
+    A(hipMemset(b.hflag, 0, (size_t)2 * g.H * kHMaxSeg));
     A(hipMemset(b.nu_w, 0, N * sizeof(double)));
     A(hipDeviceSynchronize());
     if (e != hipSuccess) {
@@ -549,7 +552,10 @@ int sgm_set_debug(sgm_context *ctx, int32_t on)
 {
     if (!ctx)
         return fail(SGM_EINVAL, "context is NULL");
-    ctx->debug = on != 0;
+    if (on & ~(SGM_DEBUG_STAGES | SGM_DEBUG_SHORT_SEGMENTS))
+        return fail(SGM_EINVAL, "unknown debug bits 0x%x", on);
+    ctx->debug = (on & SGM_DEBUG_STAGES) != 0;
+    ctx->g.hseg = (on & SGM_DEBUG_SHORT_SEGMENTS) ? 48 : 160;
     return SGM_OK;
 }
 

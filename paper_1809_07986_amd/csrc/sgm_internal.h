@@ -12,6 +12,7 @@ namespace sgmk {
 constexpr int kMaxDisp = 256;          // windows are packed as (lo, width-1) bytes
 constexpr int kMaxPaths = 8;
 constexpr int kCnnLayers = 5;          // learned window network
+constexpr int kHMaxSeg = 86;           // horizontal aggregation: segments per scanline (>= 4096 / 48)
 
 // Device-side layout of one context.  Per-pixel arrays have N = W*H
 // entries in raster order; cost-volume arrays have N*D entries (the worst
@@ -38,6 +39,7 @@ struct DevBuffers {
     uint8_t *has, *rw, *pred, *rst;
     double *dw, *pw, *dfill, *pfill;
     uint32_t *status;
+    uint8_t *hflag;            // horizontal aggregation: flagged segments [2][H][kHMaxSeg]
     // learned window (allocated in learned mode only, except nu / nu_w)
     double *nu;                // innovation of the last frame (0 without prediction)
     double *nu_w;              // previous innovation of each pixel's warp winner
@@ -52,6 +54,7 @@ struct DevBuffers {
 struct Geometry {
     int W, H, D, N;
     size_t lr_stride;          // bytes between the path-loss buffers: N*D rounded up to 256
+    int hseg;                  // horizontal aggregation: pixels per scanline segment (48 or 160)
     int cw, ch, nbits;
     int p1, p2;
     int npaths;

@@ -10,6 +10,8 @@
 // Build with -ffp-contract=off: every double-precision expression below is
 // evaluated one IEEE-754 operation at a time in the order written, so the
 // filter state is reproducible bit for bit.
+#include <stdlib.h>
+
 #include "sgm_internal.h"
 
 namespace sgmk {
@@ -621,6 +623,7 @@ struct AggArgs {
     int8_t rx[kMaxPaths], ry[kMaxPaths];
     int8_t slot[kMaxPaths];   // output buffer index of each listed path
     int kmin[kMaxPaths];      // first chain index of each listed path (k_agg_v)
+    uint8_t *hflag;           // horizontal segments whose two trajectories never met [path][H][AH2_MAXSEG]
 };
 
 constexpr int LBIG = 0x3FFF;   // "absent" predecessor term (> any L_r + P1)
@@ -1009,6 +1012,420 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
     }
 }
 
+// ---- vertical and diagonal paths, LDS-resident recurrence state ----------
+//
+// Same staging as k_agg_v (16 chains per block, 8-row batches of right census
+// and pixel metadata in LDS), but each chain keeps the previous pixel's L_r in
+// LDS, indexed by absolute disparity, and reads its d-1, d, d+1 terms back
+// masked by that pixel's window.  A pixel with a window of at most 16 cells is
+// one 16-lane chunk starting at its lower bound; a wider window is covered by
+// the 16-aligned chunks it touches.  The chunk loop runs to the largest count
+// of the wave's four chains, so a narrow step costs one chunk.
+
+constexpr int AV2_PAD = 18;   // state slots past D: chunk lanes reach lo+15, plus d+1
+
+__host__ __device__ constexpr int agg_v2_spad(int D) { return (D + AV2_PAD + 1) & ~1; }
+
+__host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
+{
+    return (size_t)2 * B * (NG + D - 1) * 8 + (size_t)2 * B * NG * sizeof(MetaEntry) +
+           (size_t)2 * NG * agg_v2_spad(D) * sizeof(uint16_t);
+}
+
+// NG chains per block (NG / 4 waves), B rows per staged batch
+template <int NG, int B>
+__global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
+{
+    constexpr int AV_NG = NG, AV_B = B, AV_T = NG * AV_G;
+    constexpr int AV_MAXCR = (AV_B * (AV_NG + kMaxDisp - 1) + AV_T - 1) / AV_T;   // per thread
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int W = a.W, H = a.H, D = a.D;
+    const int span = AV_NG + D - 1;
+    const int spad = agg_v2_spad(D);
+    uint64_t *cbuf = (uint64_t *)smem;                                            // [2][B][span]
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AV_B * span * 8);          // [2][B][NG]
+    uint16_t *sbuf = (uint16_t *)(smem + (size_t)2 * AV_B * span * 8 +
+                                  (size_t)2 * AV_B * AV_NG * sizeof(MetaEntry));  // [2][NG][spad]
+    const int pi = blockIdx.y;
+    const int k = a.slot[pi];
+    const int rx = a.rx[pi], ry = a.ry[pi];
+    const int kmin = a.kmin[pi];
+    const int nchains = rx == 0 ? W : W + H - 1;
+    if (blockIdx.x * AV_NG >= nchains)
+        return;                                        // uniform over the block
+    const int kb = kmin + blockIdx.x * AV_NG;          // chain index of group 0
+    const int grp = threadIdx.x / AV_G, lane = threadIdx.x % AV_G;
+    const int kc = kb + grp;
+    const bool chain_ok = blockIdx.x * AV_NG + grp < nchains;
+    const int ys = ry > 0 ? 0 : H - 1;
+    uint8_t *lrk = a.lr + (size_t)k * a.lr_stride;
+    const int p1 = a.p1, p2 = a.p2, nbits = a.nbits;
+    auto span_x0 = [&](int t) { return kb + rx * t - (D - 1); };
+
+    uint64_t rc[AV_MAXCR];
+    uint64_t rmcl;
+    uint32_t rmoff, rmwin;
+    auto issue = [&](int bt) {
+#pragma unroll
+        for (int i = 0; i < AV_MAXCR; i++) {
+            const int e = threadIdx.x + i * AV_T;
+            const int r = e / span, c = e - r * span;
+            const int t = bt * AV_B + r;
+            const int xx = span_x0(t) + c;
+            const bool ok = r < AV_B && t < H && xx >= 0 && xx < W;
+            const size_t idx = ok ? (size_t)(ys + ry * t) * W + xx : 0;
+            const uint64_t v = a.cr[idx];
+            rc[i] = ok ? v : 0ull;
+        }
+        {
+            const int e = threadIdx.x;   // AV_B * AV_NG <= AV_T entries
+            const int r = e / AV_NG, g = e - r * AV_NG;
+            const int t = bt * AV_B + r;
+            const int xx = kb + g + rx * t;
+            const bool ok = e < AV_B * AV_NG && t < H && xx >= 0 && xx < W;
+            const int pix = ok ? (ys + ry * t) * W + xx : 0;
+            const uint64_t vcl = a.cl[pix];
+            const uint32_t voff = a.off[pix], vwin = a.win[pix];
+            rmcl = ok ? vcl : 0ull;
+            rmoff = ok ? voff : 0u;
+            rmwin = ok ? vwin : 0u;
+        }
+    };
+    auto commit = [&](int buf) {
+        uint64_t *cb = cbuf + (size_t)buf * AV_B * span;
+#pragma unroll
+        for (int i = 0; i < AV_MAXCR; i++) {
+            const int e = threadIdx.x + i * AV_T;
+            if (e < AV_B * span)
+                cb[e] = rc[i];
+        }
+        if (threadIdx.x < AV_B * AV_NG) {
+            MetaEntry m;
+            m.cl = rmcl;
+            m.off = rmoff;
+            m.win = rmwin;
+            mbuf[buf * AV_B * AV_NG + threadIdx.x] = m;
+        }
+    };
+    issue(0);
+    commit(0);
+    __syncthreads();
+    int cur = 0;                    // state buffer holding L_r of the previous pixel
+    int mq = 0, loq = 0, hiq = -1;  // its minimum and window (empty before the first pixel)
+    bool started = false;
+    const int nbt = (H + AV_B - 1) / AV_B;
+    for (int bt = 0; bt < nbt; bt++) {
+        issue(bt + 1);
+        const uint64_t *cb = cbuf + (size_t)(bt & 1) * AV_B * span;
+        const MetaEntry *mb = mbuf + (bt & 1) * AV_B * AV_NG;
+        const int rows = min(AV_B, H - bt * AV_B);
+        for (int r = 0; r < rows; r++) {
+            const int t = bt * AV_B + r;
+            const int x = kc + rx * t;
+            const bool act = chain_ok && x >= 0 && x < W;   // uniform per group
+            const MetaEntry e = mb[r * AV_NG + grp];
+            const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
+            const bool wide = hi - lo >= AV_G;
+            const int c0 = wide ? (lo & ~(AV_G - 1)) : lo;
+            const int nt = !act ? 0 : (wide ? (hi >> 4) - (lo >> 4) + 1 : 1);
+            const int ntw = wave_max4(nt);
+            if (ntw == 0)
+                continue;                                  // uniform over the wave
+            const int qb = (cur * AV_NG + grp) * spad;     // previous pixel's L_r (slot d + 1)
+            const int pb = ((cur ^ 1) * AV_NG + grp) * spad;
+            const int cap = started ? mq + p2 : LBIG;      // the P2 term (none on the first pixel)
+            const int sub = started ? mq : 0;
+            const uint64_t *crow = cb + (size_t)r * span;
+            const int cx0 = span_x0(t);
+            int rmin = LBIG;
+            for (int j = 0; j < ntw; j++) {
+                const int d = c0 + AV_G * j + lane;
+                const bool live = j < nt && d >= lo && d <= hi;
+                const int dd = min(d, D);                  // keeps idle lanes inside the chain's slots
+                // unconditional reads; out-of-window terms become >= LBIG (absent)
+                const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
+                const uint64_t crv = crow[max(x - dd - cx0, 0)];
+                const int a0 = max(v0, (dd >= loq && dd <= hiq) ? 0 : LBIG);
+                const int am = max(vm, (dd - 1 >= loq && dd - 1 <= hiq) ? 0 : LBIG);
+                const int ap = max(vp, (dd + 1 >= loq && dd + 1 <= hiq) ? 0 : LBIG);
+                const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
+                const int pc = __popcll(e.cl ^ crv);
+                const int c = dd > x ? nbits : pc;
+                const int L = live ? c + best - sub : LBIG;
+                if (live) {
+                    sbuf[pb + dd + 1] = (uint16_t)L;
+                    lrk[e.off + (uint32_t)(dd - lo)] = (uint8_t)L;
+                }
+                rmin = min(rmin, L);
+            }
+            const int m = row_min16(rmin);
+            if (act) {
+                mq = m;
+                loq = lo;
+                hiq = hi;
+                started = true;
+            }
+            cur ^= 1;
+            wave_lds_sync();   // this step's state writes precede the next step's reads
+        }
+        commit((bt + 1) & 1);
+        __syncthreads();
+    }
+}
+
+// ---- horizontal paths: 16 scanlines per block, LDS state, segments --------
+//
+// Scanline y of a horizontal direction is cut into segments of `seg` steps
+// (step t is column rx > 0 ? t : W-1-t).  Three kernels:
+//  HS_SPEC  every segment at once, each started as if the scanline began there
+//           (segment 0 is then exact);
+//  HS_FIX   every segment s >= 1 at once, two 16-lane trajectories per
+//           scanline: A from the losses stored at the end of segment s-1, B
+//           restarted like HS_SPEC, so B reproduces the stored values.  Where A
+//           equals B at a pixel, the recurrence is deterministic and every
+//           later stored value of the segment is A's continuation; until then A
+//           writes its losses.  A scanline whose A and B never meet in the
+//           segment is flagged;
+//  HS_SEQ   for flagged scanlines only, walks the later segments in order,
+//           restarting each from the exact end of the previous one and
+//           comparing with the stored losses until they agree.
+// When no segment s-1 is flagged, the end of s-1 stored after HS_SPEC is
+// exact (by induction from segment 0), so HS_FIX made segment s exact.
+// Each block stages, per 8-step batch, its scanlines' right census over the
+// D+7 columns the batch can reach, and the pixels' metadata.
+
+enum { HS_SPEC = 0, HS_FIX = 1, HS_SEQ = 2 };
+constexpr int AH2_NG = 16, AH2_T = AH2_NG * AV_G, AH2_B = 8;
+constexpr int AH2_MAXCR = (AH2_NG * (kMaxDisp + AH2_B - 1) + AH2_T - 1) / AH2_T;   // per thread
+constexpr int AH2_MAXSEG = kHMaxSeg;
+static_assert(AH2_MAXSEG * 48 >= 4096, "segments of the widest image");
+
+__host__ __device__ constexpr int agg_h2_span(int D) { return D + AH2_B - 1; }
+
+__host__ __device__ constexpr size_t agg_h2_lds(int D)
+{
+    return (size_t)2 * AH2_NG * agg_h2_span(D) * 8 + (size_t)2 * AH2_B * AH2_NG * sizeof(MetaEntry) +
+           (size_t)2 * AH2_NG * agg_v2_spad(D) * sizeof(uint16_t);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
+{
+    constexpr int NC = MODE == HS_FIX ? AH2_NG / 2 : AH2_NG;   // scanlines per block
+    extern __shared__ __align__(16) uint8_t smem[];
+    const int W = a.W, H = a.H, D = a.D;
+    const int span = agg_h2_span(D), spad = agg_v2_spad(D);
+    uint64_t *cbuf = (uint64_t *)smem;                                               // [2][NC][span]
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AH2_NG * span * 8);           // [2][B][NC]
+    uint16_t *sbuf = (uint16_t *)((uint8_t *)mbuf + (size_t)2 * AH2_B * AH2_NG * sizeof(MetaEntry));
+    const int pi = blockIdx.z;
+    const int k = a.slot[pi];
+    const int rx = a.rx[pi];
+    const int y0 = blockIdx.x * NC;
+    const int grp = threadIdx.x / AV_G, lane = threadIdx.x % AV_G;
+    const int cg = MODE == HS_FIX ? grp >> 1 : grp;   // scanline of this group
+    const bool traj_a = MODE != HS_FIX || (grp & 1) == 0;
+    const int y = y0 + cg;
+    const bool row_ok = y < H;
+    uint8_t *lrk = a.lr + (size_t)k * a.lr_stride;
+    uint8_t *flag = a.hflag + ((size_t)pi * H + (row_ok ? y : 0)) * AH2_MAXSEG;
+    const int p1 = a.p1, p2 = a.p2, nbits = a.nbits;
+    auto colx = [&](int t) { return rx > 0 ? t : W - 1 - t; };
+    // first census column a batch starting at step tb can need
+    auto span_x0 = [&](int tb) { return rx > 0 ? tb - (D - 1) : W - tb - AH2_B - (D - 1); };
+
+    if (MODE == HS_SEQ) {
+        // nothing to do unless a scanline of the block was flagged
+        int any = 0;
+        for (int i = threadIdx.x; i < NC * AH2_MAXSEG; i += AH2_T) {
+            const int c = i / AH2_MAXSEG, sg = i % AH2_MAXSEG;
+            if (y0 + c < H && sg >= 1 && sg < nseg - 1)
+                any |= a.hflag[((size_t)pi * H + y0 + c) * AH2_MAXSEG + sg];
+        }
+        if (!__syncthreads_or(any))
+            return;
+    }
+
+    uint64_t rc[AH2_MAXCR];
+    uint64_t rmcl;
+    uint32_t rmoff, rmwin;
+    auto issue = [&](int tb, int tend) {
+        const int sx0 = span_x0(tb);
+#pragma unroll
+        for (int i = 0; i < AH2_MAXCR; i++) {
+            const int e = threadIdx.x + i * AH2_T;
+            const int c = e / span, col = e - c * span;
+            const int yy = y0 + c, xx = sx0 + col;
+            const bool ok = c < NC && yy < H && xx >= 0 && xx < W;
+            const size_t idx = ok ? (size_t)yy * W + xx : 0;
+            const uint64_t v = a.cr[idx];
+            rc[i] = ok ? v : 0ull;
+        }
+        {
+            const int e = threadIdx.x;
+            const int r = e / NC, c = e - r * NC;
+            const int t = tb + r, yy = y0 + c;
+            const bool ok = e < AH2_B * NC && t < tend && yy < H;
+            const int pix = ok ? yy * W + colx(t) : 0;
+            const uint64_t vcl = a.cl[pix];
+            const uint32_t voff = a.off[pix], vwin = a.win[pix];
+            rmcl = ok ? vcl : 0ull;
+            rmoff = ok ? voff : 0u;
+            rmwin = ok ? vwin : 0u;
+        }
+    };
+    auto commit = [&](int buf) {
+        uint64_t *cb = cbuf + (size_t)buf * AH2_NG * span;
+#pragma unroll
+        for (int i = 0; i < AH2_MAXCR; i++) {
+            const int e = threadIdx.x + i * AH2_T;
+            if (e < NC * span)
+                cb[e] = rc[i];
+        }
+        if (threadIdx.x < AH2_B * NC) {
+            MetaEntry m;
+            m.cl = rmcl;
+            m.off = rmoff;
+            m.win = rmwin;
+            mbuf[buf * AH2_B * AH2_NG + threadIdx.x] = m;
+        }
+    };
+
+    int cur = 0;                    // state buffer holding L_r of the previous pixel
+    int mq = 0, loq = 0, hiq = -1;  // its minimum and window
+    bool started = false;
+    bool done = false;              // the trajectory has met the stored losses
+    bool ran = false;               // HS_SEQ: the previous segment was recomputed to its end
+    const int s_first = MODE == HS_SPEC ? (int)blockIdx.y : MODE == HS_FIX ? (int)blockIdx.y + 1 : 2;
+    const int s_last = MODE == HS_SEQ ? nseg - 1 : s_first;
+    for (int sg = s_first; sg <= s_last; sg++) {
+        const int t0 = sg * seg, t1 = min(W, t0 + seg);
+        bool active = row_ok;       // this group works on segment sg
+        if (MODE == HS_SEQ) {
+            const bool need = row_ok && (ran || flag[sg - 1] != 0);
+            if (!__syncthreads_or(need ? 1 : 0))
+                continue;           // no scanline of the block needs this segment
+            active = need;
+        }
+        if (MODE != HS_SPEC) {
+            // exact state at the end of segment sg-1 (trajectory A): kept in
+            // LDS when HS_SEQ recomputed that segment to its end, else the
+            // stored losses.  The whole wave runs this block (cross-lane
+            // reductions inside); groups that keep their state load nothing.
+            const bool load = active && traj_a && !(MODE == HS_SEQ && ran);
+            const int p = (row_ok ? y : 0) * W + colx(t0 - 1);
+            const uint32_t wv = a.win[p];
+            const uint32_t off = a.off[p];
+            const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
+            const int nt = load ? (hi >> 4) - (lo >> 4) + 1 : 0;
+            const int ntw = wave_max4(nt);
+            const int qb = (cur * AH2_NG + grp) * spad;
+            int rmin = LBIG;
+            for (int j = 0; j < ntw; j++) {
+                const int d = (lo & ~(AV_G - 1)) + AV_G * j + lane;
+                if (j < nt && d >= lo && d <= hi) {
+                    const int v = lrk[off + (uint32_t)(d - lo)];
+                    sbuf[qb + d + 1] = (uint16_t)v;
+                    rmin = min(rmin, v);
+                }
+            }
+            const int m = row_min16(rmin);
+            if (load) {
+                mq = m;
+                loq = lo;
+                hiq = hi;
+                started = true;
+            }
+            if (MODE == HS_FIX && !traj_a)
+                started = false;    // trajectory B restarts like HS_SPEC
+            wave_lds_sync();
+        }
+        done = !active;
+        issue(t0, t1);
+        commit(0);
+        __syncthreads();
+        const int nbt = (t1 - t0 + AH2_B - 1) / AH2_B;
+        for (int bt = 0; bt < nbt; bt++) {
+            const int tb = t0 + bt * AH2_B;
+            if (bt + 1 < nbt)
+                issue(tb + AH2_B, t1);
+            const uint64_t *crow = cbuf + (size_t)(bt & 1) * AH2_NG * span + (size_t)cg * span;
+            const MetaEntry *mb = mbuf + (bt & 1) * AH2_B * AH2_NG;
+            const int cx0 = span_x0(tb);
+            const int rows = min(AH2_B, t1 - tb);
+            for (int r = 0; r < rows; r++) {
+                const int x = colx(tb + r);
+                const bool act = row_ok && !done;            // uniform per group (and per scanline in HS_FIX)
+                const MetaEntry e = mb[r * NC + cg];
+                const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
+                const bool wide = hi - lo >= AV_G;
+                const int c0 = wide ? (lo & ~(AV_G - 1)) : lo;
+                const int nt = !act ? 0 : (wide ? (hi >> 4) - (lo >> 4) + 1 : 1);
+                const int ntw = wave_max4(nt);
+                if (ntw == 0)
+                    continue;                                  // uniform over the wave
+                const int qb = (cur * AH2_NG + grp) * spad;
+                const int pb = ((cur ^ 1) * AH2_NG + grp) * spad;
+                const int cap = started ? mq + p2 : LBIG;
+                const int sub = started ? mq : 0;
+                int rmin = LBIG;
+                bool diff = false;
+                for (int j = 0; j < ntw; j++) {
+                    const int d = c0 + AV_G * j + lane;
+                    const bool live = j < nt && d >= lo && d <= hi;
+                    const int dd = min(d, D);
+                    const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
+                    const uint64_t crv = crow[max(x - dd - cx0, 0)];
+                    const int a0 = max(v0, (dd >= loq && dd <= hiq) ? 0 : LBIG);
+                    const int am = max(vm, (dd - 1 >= loq && dd - 1 <= hiq) ? 0 : LBIG);
+                    const int ap = max(vp, (dd + 1 >= loq && dd + 1 <= hiq) ? 0 : LBIG);
+                    const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
+                    const int pc = __popcll(e.cl ^ crv);
+                    const int c = dd > x ? nbits : pc;
+                    const int L = live ? c + best - sub : LBIG;
+                    if (MODE == HS_FIX) {
+                        // lane i of trajectory A sits 16 lanes below lane i of B
+                        const int other = __shfl_xor(L, AV_G, 64);
+                        diff = diff || (live && other != L);
+                    }
+                    if (live) {
+                        uint8_t *dst = lrk + e.off + (uint32_t)(dd - lo);
+                        if (MODE == HS_SEQ)
+                            diff = diff || (*dst != (uint8_t)L);
+                        sbuf[pb + dd + 1] = (uint16_t)L;
+                        if (traj_a)
+                            *dst = (uint8_t)L;
+                    }
+                    rmin = min(rmin, L);
+                }
+                const int m = row_min16(rmin);
+                if (act) {
+                    mq = m;
+                    loq = lo;
+                    hiq = hi;
+                    started = true;
+                    if (MODE != HS_SPEC && row_min16(diff ? 0 : 1) == 1)
+                        done = true;   // stored losses agree from here on
+                }
+                cur ^= 1;
+                wave_lds_sync();
+            }
+            if (MODE != HS_SPEC) {
+                if (!__syncthreads_or(row_ok && !done ? 1 : 0))
+                    break;   // every scanline of the block has met the stored losses
+            }
+            if (bt + 1 < nbt)
+                commit((bt + 1) & 1);
+            __syncthreads();
+        }
+        if (MODE == HS_FIX && traj_a && lane == 0 && row_ok)
+            flag[sg] = done ? 0 : 1;
+        if (MODE == HS_SEQ)
+            ran = active && !done;
+        __syncthreads();   // staging buffers are rewritten by the next segment
+    }
+}
+
 static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv, int &nh, int &nv, int &maxv)
 {
     for (AggArgs *a : {&hv, &vv}) {
@@ -1018,6 +1435,7 @@ static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv,
         a->off = b.off;
         a->lr = b.lr;
         a->lr_stride = g.lr_stride;
+        a->hflag = b.hflag;
         a->W = g.W;
         a->H = g.H;
         a->D = g.D;
@@ -1044,6 +1462,14 @@ static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv,
     }
 }
 
+// dynamic LDS beyond 64 KB must be requested per kernel (gfx950 has 160 KB per CU)
+static hipError_t allow_lds(const void *fn, size_t bytes)
+{
+    if (bytes <= 65536)
+        return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 int count_horizontal_paths(const Geometry &g)
 {
     int n = 0;
@@ -1059,6 +1485,27 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s)
     agg_args(g, b, hv, vv, nh, nv, maxv);
     if (!nh)
         return hipSuccess;
+    if (!getenv("SGMK_AGG_H1")) {
+        const int seg = g.hseg;
+        const int nseg = (g.W + seg - 1) / seg;
+        const size_t lds2 = agg_h2_lds(g.D);
+        hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC>, lds2);
+        if (e == hipSuccess)
+            e = allow_lds((const void *)k_agg_h2<HS_FIX>, lds2);
+        if (e == hipSuccess)
+            e = allow_lds((const void *)k_agg_h2<HS_SEQ>, lds2);
+        if (e != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_agg_h2<HS_SPEC>), dim3((g.H + AH2_NG - 1) / AH2_NG, nseg, nh), dim3(AH2_T), lds2, s,
+                           hv, seg, nseg);
+        if (nseg > 1)
+            hipLaunchKernelGGL((k_agg_h2<HS_FIX>), dim3((g.H + AH2_NG / 2 - 1) / (AH2_NG / 2), nseg - 1, nh),
+                               dim3(AH2_T), lds2, s, hv, seg, nseg);
+        if (nseg > 2)
+            hipLaunchKernelGGL((k_agg_h2<HS_SEQ>), dim3((g.H + AH2_NG - 1) / AH2_NG, 1, nh), dim3(AH2_T), lds2, s,
+                               hv, seg, nseg);
+        return hipGetLastError();
+    }
     size_t lds = agg_h_lds(g.W);
     dim3 grd(g.H, nh);
     if (g.D <= 64)
@@ -1077,14 +1524,18 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s)
     agg_args(g, b, hv, vv, nh, nv, maxv);
     if (!nv)
         return hipSuccess;
-    size_t lds = agg_v_lds(g.D);
     dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
-    if (g.D <= 64)
-        hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
-    else if (g.D <= 128)
-        hipLaunchKernelGGL((k_agg_v<8>), grd, dim3(AV_T), lds, s, vv);
-    else
-        hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
+    if (getenv("SGMK_AGG_V1")) {
+        size_t lds = agg_v_lds(g.D);
+        if (g.D <= 64)
+            hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
+        else if (g.D <= 128)
+            hipLaunchKernelGGL((k_agg_v<8>), grd, dim3(AV_T), lds, s, vv);
+        else
+            hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_agg_v2<16, 8>), grd, dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
     return hipGetLastError();
 }
 

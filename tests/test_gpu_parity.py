@@ -260,6 +260,25 @@ def test_deterministic_repeat():
         assert np.array_equal(a, b)
 
 
+def test_short_horizontal_segments_change_nothing():
+    # 48-pixel segments: more segment starts, some whose restarted and exact
+    # trajectories do not meet inside the segment (sequential fix-up pass)
+    seq = synth.make_sequence("driving", frames=3)
+    H, W = seq.cam.height, seq.cam.width
+    outs = []
+    for dbg in (0, NAT.DEBUG_SHORT_SEGMENTS):
+        _say(f"case: driving, debug {dbg}")
+        g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+        g.set_debug(dbg)
+        g.full_frame(seq.left[0], seq.right[0])
+        for k in (1, 2):
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        torch.cuda.synchronize()
+        outs.append([_np(g.stage(NAT.STAGE_PATH0 + k)) for k in (0, 1)] + [_np(t) for t in g.get_state()])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_driving_full_size_sequence():
     # the benchmark workload at full size (1242x375, D=128): census, the full
     # frame and two reduced frames against the oracle, every pixel
