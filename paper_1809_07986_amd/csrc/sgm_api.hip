@@ -221,13 +221,13 @@ int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pi
             return hip_fail(e, "stream fork");
         StageMark mh(marks ? ctx->prof : g_noprof, ctx->side);
         mh.begin(SGM_PROF_AGG_H);
-        e = launch_agg_h(g, b, ctx->side);
+        e = launch_agg_h(g, b, mode == 0, ctx->side);
         mh.end(SGM_PROF_AGG_H);
         if (e != hipSuccess)
             return hip_fail(e, "horizontal aggregation launch");
     }
     mk.begin(SGM_PROF_AGG_V);
-    e = launch_agg_v(g, b, s);
+    e = launch_agg_v(g, b, mode == 0, s);
     mk.end(SGM_PROF_AGG_V);
     if (e != hipSuccess)
         return hip_fail(e, "aggregation launch");

@@ -84,8 +84,9 @@ hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
 // vertical + diagonal paths (16 scanlines per block); the two launches are
 // independent and may run on different streams.
 int count_horizontal_paths(const Geometry &g);
-hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s);
-hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s);
+// dense: every window is the full range (the full-frame kernels)
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s);
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s);
 // mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only;
 // rpix: per-pixel measurement variance (NULL: cc.r)
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,

@@ -10,7 +10,6 @@
 // Build with -ffp-contract=off: every double-precision expression below is
 // evaluated one IEEE-754 operation at a time in the order written, so the
 // filter state is reproducible bit for bit.
-#include <stdlib.h>
 
 #include "sgm_internal.h"
 
@@ -1478,14 +1477,14 @@ int count_horizontal_paths(const Geometry &g)
     return n;
 }
 
-hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s)
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s)
 {
     AggArgs hv, vv;
     int nh, nv, maxv;
     agg_args(g, b, hv, vv, nh, nv, maxv);
     if (!nh)
         return hipSuccess;
-    if (!getenv("SGMK_AGG_H1")) {
+    if (!dense) {
         const int seg = g.hseg;
         const int nseg = (g.W + seg - 1) / seg;
         const size_t lds2 = agg_h2_lds(g.D);
@@ -1517,15 +1516,16 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s)
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s)
 {
     AggArgs hv, vv;
     int nh, nv, maxv;
     agg_args(g, b, hv, vv, nh, nv, maxv);
     if (!nv)
         return hipSuccess;
-    dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
-    if (getenv("SGMK_AGG_V1")) {
+    if (dense) {
+        // every window is the full range: 16 scanlines per block, lanes by disparity
+        dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
         size_t lds = agg_v_lds(g.D);
         if (g.D <= 64)
             hipLaunchKernelGGL((k_agg_v<4>), grd, dim3(AV_T), lds, s, vv);
@@ -1535,6 +1535,8 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, hipStream_t s)
             hipLaunchKernelGGL((k_agg_v<16>), grd, dim3(AV_T), lds, s, vv);
         return hipGetLastError();
     }
+    // ragged windows: LDS-resident state, chunk count per pixel
+    dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
     hipLaunchKernelGGL((k_agg_v2<16, 8>), grd, dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
     return hipGetLastError();
 }
