@@ -20,7 +20,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux",
+__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux", "median3x3",
            "learned_windows", "correct", "correct_ex", "OracleFilter", "PRED", "RESET", "FULLWIN", "GATEFAIL",
            "PATH_DX", "PATH_DY"]
 
@@ -114,9 +114,10 @@ def _load():
             lib.orc_predict_aux.argtypes = [P] * 12
             lib.orc_learned_windows.argtypes = [P] * 6
             lib.orc_correct_ex.argtypes = [P] * 14
+            lib.orc_median3x3.argtypes = [P, i, i, P]
             for name in ("orc_census", "orc_cost", "orc_aggregate", "orc_wta", "orc_match", "orc_predict",
                          "orc_correct", "orc_full_frame", "orc_reduced_frame", "orc_predict_aux",
-                         "orc_learned_windows", "orc_correct_ex"):
+                         "orc_learned_windows", "orc_correct_ex", "orc_median3x3"):
                 getattr(lib, name).restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -262,6 +263,15 @@ def correct_ex(prm: Params, dhat, pm, flags, lo, hi, dstar, dz, rpix=None):
     _check(_load().orc_correct_ex(ctypes.byref(cp), _p(dhat), _p(pm), _p(flags), _p(lo), _p(hi), _p(dstar),
                                   _p(dz), _p(rp), _p(d), _p(p), _p(mask), _p(sflags), _p(nu)), "correct_ex")
     return d, p, mask, sflags, nu
+
+
+def median3x3(d) -> np.ndarray:
+    """3x3 block median with clamped borders (Section 2.3 post-processing)."""
+    d = _c(d, np.float64)
+    H, W = d.shape
+    out = np.zeros((H, W), np.float64)
+    _check(_load().orc_median3x3(_p(d), W, H, _p(out)), "median3x3")
+    return out
 
 
 def correct(prm: Params, dhat, pm, flags, lo, hi, dstar, dz):

@@ -575,3 +575,34 @@ int orc_reduced_frame(const orc_params *prm, const uint8_t *left, const uint8_t 
         return rc;
     return orc_correct(prm, dhat, pm, flags, lo, hi, dstar, dz, d, p, mask, sflags);
 }
+
+/* ------------------------------------------------------------------------
+ * Post-processing (Section 2.3): 3x3 block median of the filtered disparity,
+ * outside the Kalman loop (the state is not changed).  Reading: neighbours
+ * outside the image are clamped to the edge, so every pixel takes the median
+ * (5th smallest) of 9 values.
+ * ---------------------------------------------------------------------- */
+int orc_median3x3(const double *d, int W, int H, double *out)
+{
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            double v[9];
+            int n = 0;
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++)
+                    v[n++] = d[clampi(y + dy, 0, H - 1) * W + clampi(x + dx, 0, W - 1)];
+            /* insertion sort of 9 values */
+            for (int i = 1; i < 9; i++) {
+                double t = v[i];
+                int j = i - 1;
+                while (j >= 0 && v[j] > t) {
+                    v[j + 1] = v[j];
+                    j--;
+                }
+                v[j + 1] = t;
+            }
+            out[y * W + x] = v[4];
+        }
+    }
+    return 0;
+}

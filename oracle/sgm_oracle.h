@@ -49,6 +49,7 @@ int orc_learned_windows(const orc_params *prm, const double *dhat, const double 
 int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
                    const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                    const double *rpix, double *d, double *p, uint8_t *mask, uint8_t *sflags, double *nu_out);
+int orc_median3x3(const double *d, int W, int H, double *out);
 int orc_correct(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
                 const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                 double *d, double *p, uint8_t *mask, uint8_t *sflags);
