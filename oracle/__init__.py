@@ -21,6 +21,7 @@ from typing import Optional
 import numpy as np
 
 __all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux", "median3x3",
+           "DetectParams", "motion_values", "integral", "detect_windows", "merge_boxes", "detect",
            "learned_windows", "correct", "correct_ex", "OracleFilter", "PRED", "RESET", "FULLWIN", "GATEFAIL",
            "PATH_DX", "PATH_DY"]
 
@@ -115,9 +116,15 @@ def _load():
             lib.orc_learned_windows.argtypes = [P] * 6
             lib.orc_correct_ex.argtypes = [P] * 14
             lib.orc_median3x3.argtypes = [P, i, i, P]
+            lib.orc_motion_values.argtypes = [P, P, P, i, i, i, i, P]
+            lib.orc_integral.argtypes = [P, i, i, P]
+            lib.orc_detect_windows.argtypes = [P, P, i, i, P, P]
+            lib.orc_merge_boxes.argtypes = [P, i, ctypes.c_double, ctypes.c_int64]
+            lib.orc_detect.argtypes = [P, P, P, P, i, i, P, P]
             for name in ("orc_census", "orc_cost", "orc_aggregate", "orc_wta", "orc_match", "orc_predict",
                          "orc_correct", "orc_full_frame", "orc_reduced_frame", "orc_predict_aux",
-                         "orc_learned_windows", "orc_correct_ex", "orc_median3x3"):
+                         "orc_learned_windows", "orc_correct_ex", "orc_median3x3", "orc_motion_values",
+                         "orc_integral", "orc_detect_windows", "orc_merge_boxes", "orc_detect"):
                 getattr(lib, name).restype = ctypes.c_int
             _lib = lib
     return _lib
@@ -272,6 +279,84 @@ def median3x3(d) -> np.ndarray:
     out = np.zeros((H, W), np.float64)
     _check(_load().orc_median3x3(_p(d), W, H, _p(out)), "median3x3")
     return out
+
+
+class _CDetect(ctypes.Structure):
+    _fields_ = [("top", ctypes.c_int32), ("n_sizes", ctypes.c_int32), ("sizes", (ctypes.c_int32 * 2) * 8),
+                ("scale", ctypes.c_int32), ("cap", ctypes.c_int32), ("thresh", ctypes.c_int32),
+                ("max_detections", ctypes.c_int32), ("min_area", ctypes.c_int64), ("merge_iou", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class DetectParams:
+    """Moving-object detection settings (Section 4); `top` None = height // 3."""
+    sizes: tuple = ((20, 20), (30, 30), (40, 40), (50, 50), (50, 75))
+    top: Optional[int] = None
+    scale: int = 16
+    cap: int = 256
+    thresh: int = 16
+    max_detections: int = 2048
+    min_area: int = 1600
+    merge_iou: float = 0.0
+
+    def c(self, height: int) -> _CDetect:
+        out = _CDetect()
+        out.top = height // 3 if self.top is None else self.top
+        out.n_sizes = len(self.sizes)
+        for k, (w, h) in enumerate(self.sizes):
+            out.sizes[k][0], out.sizes[k][1] = w, h
+        out.scale, out.cap, out.thresh = self.scale, self.cap, self.thresh
+        out.max_detections, out.min_area, out.merge_iou = self.max_detections, self.min_area, self.merge_iou
+        return out
+
+
+def motion_values(dhat, dz, flags, scale: int = 16, cap: int = 256) -> np.ndarray:
+    """Fixed-point |d^ - d_z| where a prediction exists, else 0 (Section 4)."""
+    dhat, dz, flags = _c(dhat, np.float64), _c(dz, np.float64), _c(flags, np.uint8)
+    H, W = dhat.shape
+    v = np.zeros((H, W), np.int32)
+    _check(_load().orc_motion_values(_p(dhat), _p(dz), _p(flags), W, H, scale, cap, _p(v)), "motion_values")
+    return v
+
+
+def integral(v) -> np.ndarray:
+    """(H+1) x (W+1) summed-area table of an int32 map."""
+    v = _c(v, np.int32)
+    H, W = v.shape
+    S = np.zeros((H + 1, W + 1), np.int64)
+    _check(_load().orc_integral(_p(v), W, H, _p(S)), "integral")
+    return S
+
+
+def detect_windows(S, dp: DetectParams):
+    """Sliding-window detections (k x 4 half-open boxes) and the number that fired."""
+    S = _c(S, np.int64)
+    H, W = S.shape[0] - 1, S.shape[1] - 1
+    c = dp.c(H)
+    boxes = np.zeros((max(dp.max_detections, 1), 4), np.int32)
+    fired = ctypes.c_int32(0)
+    n = _load().orc_detect_windows(ctypes.byref(c), _p(S), W, H, _p(boxes), ctypes.byref(fired))
+    return boxes[:n].copy(), fired.value
+
+
+def merge_boxes(boxes, merge_iou: float = 0.0, min_area: int = 0) -> np.ndarray:
+    """Greedy IoU grouping followed by the small-box discard."""
+    b = _c(np.asarray(boxes).reshape(-1, 4), np.int32).copy()
+    n = _load().orc_merge_boxes(_p(b), b.shape[0], float(merge_iou), int(min_area))
+    return b[:n].copy()
+
+
+def detect(dhat, dz, flags, dp: Optional[DetectParams] = None):
+    """Moving-object boxes of one frame and the number of windows that fired."""
+    dp = dp or DetectParams()
+    dhat, dz, flags = _c(dhat, np.float64), _c(dz, np.float64), _c(flags, np.uint8)
+    H, W = dhat.shape
+    c = dp.c(H)
+    boxes = np.zeros((max(dp.max_detections, 1), 4), np.int32)
+    fired = ctypes.c_int32(0)
+    n = _load().orc_detect(ctypes.byref(c), _p(dhat), _p(dz), _p(flags), W, H, _p(boxes), ctypes.byref(fired))
+    _check(0 if n >= 0 else n, "detect")
+    return boxes[:n].copy(), fired.value
 
 
 def correct(prm: Params, dhat, pm, flags, lo, hi, dstar, dz):

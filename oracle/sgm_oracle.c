@@ -606,3 +606,158 @@ int orc_median3x3(const double *d, int W, int H, double *out)
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Moving-object detection (Section 4).
+ *
+ * Readings (the paper gives the structure, not every constant):
+ *  - the difference map is |d^ - d_z| where the frame has a prediction
+ *    (ORC_PRED) whose correspondence x - d^ lies inside the right image, and
+ *    0 elsewhere (no measurement is possible left of that), in fixed point:
+ *    floor(|d^ - d_z| * scale) capped at `cap`, so window sums are exact
+ *    integers;
+ *  - a window "is high relative to its area" when its sum is at least
+ *    thresh * area (thresh in the same fixed-point units per pixel);
+ *  - windows of every listed size slide with a step of half their width and
+ *    half their height, from row `top` (the bottom two thirds: top = H/3) to
+ *    the bottom edge; detections are listed by size, then row, then column,
+ *    and at most max_detections are kept;
+ *  - the greedy grouping merges the pair with the highest intersection over
+ *    union (exact rational comparison; ties: the pair that comes first in
+ *    list order) into its bounding box, in the place of the earlier box,
+ *    while that IoU exceeds merge_iou;
+ *  - boxes with an area below min_area are then discarded.
+ * Boxes are half-open [x0, x1) x [y0, y1).
+ * ---------------------------------------------------------------------- */
+int orc_motion_values(const double *dhat, const double *dz, const uint8_t *flags, int W, int H, int scale,
+                      int cap, int32_t *v)
+{
+    for (int y = 0; y < H; y++) {
+        for (int x = 0; x < W; x++) {
+            const int i = y * W + x;
+            if ((flags[i] & ORC_PRED) && (double)x - dhat[i] >= 0.0)
+                v[i] = (int32_t)fmin(floor(fabs(dhat[i] - dz[i]) * (double)scale), (double)cap);
+            else
+                v[i] = 0;
+        }
+    }
+    return 0;
+}
+
+/* Summed-area table: S[y][x] = sum of v over rows < y and columns < x
+ * ((H+1) x (W+1) entries), so any box sum takes four lookups
+ * (inclusion-exclusion). */
+int orc_integral(const int32_t *v, int W, int H, int64_t *S)
+{
+    for (int x = 0; x <= W; x++)
+        S[x] = 0;
+    for (int y = 1; y <= H; y++) {
+        int64_t row = 0;
+        S[(size_t)y * (W + 1)] = 0;
+        for (int x = 1; x <= W; x++) {
+            row += v[(size_t)(y - 1) * W + (x - 1)];
+            S[(size_t)y * (W + 1) + x] = S[(size_t)(y - 1) * (W + 1) + x] + row;
+        }
+    }
+    return 0;
+}
+
+static int64_t box_sum(const int64_t *S, int W, int x0, int y0, int x1, int y1)
+{
+    const size_t s = (size_t)W + 1;
+    return S[(size_t)y1 * s + x1] - S[(size_t)y0 * s + x1] - S[(size_t)y1 * s + x0] + S[(size_t)y0 * s + x0];
+}
+
+int orc_detect_windows(const orc_detect_params *dp, const int64_t *S, int W, int H, int32_t *boxes,
+                       int32_t *n_fired)
+{
+    int kept = 0, fired = 0;
+    for (int s = 0; s < dp->n_sizes; s++) {
+        const int w = dp->sizes[s][0], h = dp->sizes[s][1];
+        const int sx = w / 2 > 0 ? w / 2 : 1, sy = h / 2 > 0 ? h / 2 : 1;
+        for (int y0 = dp->top; y0 + h <= H; y0 += sy) {
+            for (int x0 = 0; x0 + w <= W; x0 += sx) {
+                int64_t sum = box_sum(S, W, x0, y0, x0 + w, y0 + h);
+                if (sum >= (int64_t)dp->thresh * w * h) {
+                    fired++;
+                    if (kept < dp->max_detections) {
+                        boxes[4 * kept + 0] = x0;
+                        boxes[4 * kept + 1] = y0;
+                        boxes[4 * kept + 2] = x0 + w;
+                        boxes[4 * kept + 3] = y0 + h;
+                        kept++;
+                    }
+                }
+            }
+        }
+    }
+    *n_fired = fired;
+    return kept;
+}
+
+static int64_t box_area(const int32_t *b) { return (int64_t)(b[2] - b[0]) * (b[3] - b[1]); }
+
+static int64_t box_inter(const int32_t *a, const int32_t *b)
+{
+    int64_t w = (int64_t)(a[2] < b[2] ? a[2] : b[2]) - (a[0] > b[0] ? a[0] : b[0]);
+    int64_t h = (int64_t)(a[3] < b[3] ? a[3] : b[3]) - (a[1] > b[1] ? a[1] : b[1]);
+    return w > 0 && h > 0 ? w * h : 0;
+}
+
+/* Greedy grouping on a list of n boxes (in place); returns the number left. */
+int orc_merge_boxes(int32_t *boxes, int n, double merge_iou, int64_t min_area)
+{
+    while (n >= 2) {
+        int bi = -1, bj = -1;
+        int64_t bI = 0, bU = 1;
+        for (int i = 0; i < n; i++) {
+            for (int j = i + 1; j < n; j++) {
+                int64_t I = box_inter(boxes + 4 * i, boxes + 4 * j);
+                int64_t U = box_area(boxes + 4 * i) + box_area(boxes + 4 * j) - I;
+                /* I / U > bI / bU, exactly */
+                if (bi < 0 || I * bU > bI * U) {
+                    bi = i;
+                    bj = j;
+                    bI = I;
+                    bU = U;
+                }
+            }
+        }
+        if (!((double)bI > merge_iou * (double)bU))
+            break;
+        int32_t *a = boxes + 4 * bi, *b = boxes + 4 * bj;
+        if (b[0] < a[0]) a[0] = b[0];
+        if (b[1] < a[1]) a[1] = b[1];
+        if (b[2] > a[2]) a[2] = b[2];
+        if (b[3] > a[3]) a[3] = b[3];
+        memmove(boxes + 4 * bj, boxes + 4 * (bj + 1), sizeof(int32_t) * 4 * (size_t)(n - bj - 1));
+        n--;
+    }
+    int m = 0;
+    for (int i = 0; i < n; i++) {
+        if (box_area(boxes + 4 * i) >= min_area) {
+            memmove(boxes + 4 * m, boxes + 4 * i, sizeof(int32_t) * 4);
+            m++;
+        }
+    }
+    return m;
+}
+
+int orc_detect(const orc_detect_params *dp, const double *dhat, const double *dz, const uint8_t *flags, int W,
+               int H, int32_t *boxes, int32_t *n_fired)
+{
+    int32_t *v = (int32_t *)malloc(sizeof(int32_t) * (size_t)W * H);
+    int64_t *S = (int64_t *)malloc(sizeof(int64_t) * (size_t)(W + 1) * (H + 1));
+    if (!v || !S) {
+        free(v);
+        free(S);
+        return -1;
+    }
+    orc_motion_values(dhat, dz, flags, W, H, dp->scale, dp->cap, v);
+    orc_integral(v, W, H, S);
+    int n = orc_detect_windows(dp, S, W, H, boxes, n_fired);
+    n = orc_merge_boxes(boxes, n, dp->merge_iou, dp->min_area);
+    free(v);
+    free(S);
+    return n;
+}

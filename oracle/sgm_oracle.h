@@ -50,6 +50,26 @@ int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, 
                    const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                    const double *rpix, double *d, double *p, uint8_t *mask, uint8_t *sflags, double *nu_out);
 int orc_median3x3(const double *d, int W, int H, double *out);
+
+/* moving-object detection (Section 4) */
+typedef struct {
+    int32_t top;                 /* first row the windows cover */
+    int32_t n_sizes;             /* window sizes in use (<= 8) */
+    int32_t sizes[8][2];         /* width, height */
+    int32_t scale, cap, thresh;  /* fixed point of |d^ - d_z|, per-pixel cap, firing level */
+    int32_t max_detections;      /* windows kept for grouping */
+    int64_t min_area;            /* smaller final boxes are discarded */
+    double merge_iou;            /* merge while the best IoU exceeds this */
+} orc_detect_params;
+
+int orc_motion_values(const double *dhat, const double *dz, const uint8_t *flags, int W, int H, int scale,
+                      int cap, int32_t *v);
+int orc_integral(const int32_t *v, int W, int H, int64_t *S);
+int orc_detect_windows(const orc_detect_params *dp, const int64_t *S, int W, int H, int32_t *boxes,
+                       int32_t *n_fired);
+int orc_merge_boxes(int32_t *boxes, int n, double merge_iou, int64_t min_area);
+int orc_detect(const orc_detect_params *dp, const double *dhat, const double *dz, const uint8_t *flags, int W,
+               int H, int32_t *boxes, int32_t *n_fired);
 int orc_correct(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,
                 const int32_t *lo, const int32_t *hi, const int32_t *dstar, const double *dz,
                 double *d, double *p, uint8_t *mask, uint8_t *sflags);
