@@ -81,6 +81,12 @@ typedef struct {
  * SGM_WIN_KSIGMA windows, no gate re-run. */
 int sgm_default_params(sgm_params *out, int32_t width, int32_t height, int32_t max_disp);
 
+/* The settings of the paper's evaluation (Table 1, "proposed"): census 5x5,
+ * P1=6, P2=65, 8 paths (set path_mask to 0x0F for the nondiagonal 4-path
+ * and 0xF0 for the diagonal 4-path variant of Section 5); Table 1 matches
+ * max_disp=128.  Everything else as sgm_default_params. */
+int sgm_paper_params(sgm_params *out, int32_t width, int32_t height, int32_t max_disp);
+
 /* Validate `prm` and allocate a context with every device buffer it will
  * need (worst case: all windows full range).  Synchronous. */
 int sgm_create(const sgm_params *prm, sgm_context **out);
@@ -110,6 +116,14 @@ int sgm_reduced_frame(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
 int sgm_get_disparity(sgm_context *ctx, float *out, int32_t out_pitch, void *stream);
 int sgm_get_variance(sgm_context *ctx, float *out, int32_t out_pitch, void *stream);
 int sgm_get_motion_mask(sgm_context *ctx, uint8_t *out, int32_t out_pitch, void *stream);
+
+/* Post-processing of Section 2.3: the 3x3 block median of the current
+ * filtered disparity d^k, written as float32 into `out` (device, out_pitch
+ * elements per row, caller-owned).  Neighbours outside the image are the
+ * nearest edge pixel.  The filter state is not changed (the median stays
+ * outside the Kalman loop).  SGM_EINVAL for a NULL `out` or a pitch below
+ * the width. */
+int sgm_get_disparity_median(sgm_context *ctx, float *out, int32_t out_pitch, void *stream);
 
 /* Filter state (checkpoint / restore): d, p as float64 and the per-pixel
  * RESET flags, dense width*height arrays. */
@@ -290,6 +304,79 @@ int sgm_batch_step(sgm_batch *b, const double *T, void *stream);
 int sgm_batch_step_graph(sgm_batch *b, const double *T, void *stream);
 int sgm_batch_set_schedule(sgm_batch *b, int32_t lanes, int32_t order);
 int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *chosen, void *stream);
+
+/* ---- moving-object detection (Section 4) --------------------------------
+ * Moving objects are where the predicted and the measured disparity
+ * disagree.  Per frame:
+ *  1. difference map v = min(floor(|d^ - d_z| * scale), cap) where the pixel
+ *     has a prediction (SGM_FLAG_PRED) whose correspondence x - d^ lies
+ *     inside the right image, else 0 (fixed point, so sums are exact);
+ *  2. summed-area table of v over rows [top, height) (constant-time window
+ *     sums by inclusion-exclusion);
+ *  3. every window of every size, stepped by half its width and half its
+ *     height from (0, top), fires when its sum >= thresh * its area; fired
+ *     windows are listed by size, then row, then column, and the first
+ *     max_detections are kept;
+ *  4. greedy grouping: while the pair of boxes with the highest
+ *     intersection over union has IoU > merge_iou, the earlier box of the
+ *     pair becomes the bounding box of both and the later one is removed
+ *     (ties: the pair that comes first in list order);
+ *  5. boxes with an area below min_area are discarded.
+ * Boxes are int32 [x0, y0, x1, y1], half-open, in list order. */
+#define SGM_DETECT_MAX_SIZES 8
+#define SGM_DETECT_MAX 2048   /* largest max_detections */
+
+typedef struct {
+    int32_t top;                 /* first row covered (sgm_detect_default_params: height / 3) */
+    int32_t n_sizes;             /* 1..SGM_DETECT_MAX_SIZES */
+    int32_t sizes[SGM_DETECT_MAX_SIZES][2];   /* window width, height */
+    int32_t scale;               /* fixed-point units per pixel of disparity difference, >= 1 */
+    int32_t cap;                 /* per-pixel cap (units), >= 1; width*height*cap < 2^32 per size */
+    int32_t thresh;              /* firing level (units per pixel of window area), >= 0 */
+    int32_t max_detections;      /* 1..SGM_DETECT_MAX */
+    int64_t min_area;            /* smallest kept box (px), >= 0 */
+    double merge_iou;            /* 0 <= merge_iou <= 1 */
+} sgm_detect_params;
+
+typedef struct sgm_detector sgm_detector;
+
+/* Defaults: windows 20x20, 30x30, 40x40, 50x50 and 50x75 (the range the
+ * paper names), the bottom two thirds (top = height / 3), 1/16 px units
+ * capped at 16 px, firing at a mean difference of 1 px, merge while any
+ * two boxes overlap, discard boxes under 40x40 px, keep 2048 windows. */
+int sgm_detect_default_params(sgm_detect_params *out, int32_t width, int32_t height);
+
+/* A detector for width x height frames (same limits as sgm_params) owns
+ * its scratch (a (height - top + 1) x (width + 1) uint32 table and one byte
+ * per window) on the current device.  SGM_EINVAL for out-of-range settings,
+ * SGM_ENOMEM if the allocation fails. */
+int sgm_detector_create(int32_t width, int32_t height, const sgm_detect_params *prm, sgm_detector **out);
+void sgm_detector_destroy(sgm_detector *det);
+
+/* Number of sliding windows tested per frame (host only). */
+int sgm_detector_windows(sgm_detector *det, int64_t *n);
+
+/* Detect on caller arrays: dhat, dz float64 and flags uint8, dense
+ * width*height device arrays (the SGM_STAGE_DHAT, _DZ and _FLAGS layouts).
+ * Writes up to max_detections boxes to `boxes` (device int32, 4 per box)
+ * and count[0] = boxes written, count[1] = windows that fired (before the
+ * max_detections cut) to `count` (device int32[2]). */
+int sgm_detect(sgm_detector *det, const double *dhat, const double *dz, const uint8_t *flags, int32_t *boxes,
+               int32_t *count, void *stream);
+
+/* The same on the last frame of a context (created with the same width and
+ * height on the same device).  After a full frame there is no prediction
+ * and no box. */
+int sgm_detect_frame(sgm_detector *det, sgm_context *ctx, int32_t *boxes, int32_t *count, void *stream);
+
+/* Intermediate results of the last sgm_detect / sgm_detect_frame, copied to
+ * device memory `out` of at least the stated size:
+ *   SGM_DSTAGE_SAT    uint32 (height - top + 1) x (width + 1): row r, column
+ *                     x holds the sum of v over rows [top, top + r) and
+ *                     columns [0, x), modulo 2^32
+ *   SGM_DSTAGE_FIRED  uint8 per window (window order as in step 3) */
+enum { SGM_DSTAGE_SAT = 0, SGM_DSTAGE_FIRED = 1 };
+int sgm_detector_stage(sgm_detector *det, int32_t stage, void *out, size_t bytes, void *stream);
 
 /* Thread-local message describing the last nonzero return on this thread. */
 const char *sgm_last_error(void);

@@ -19,7 +19,8 @@ import torch
 
 from . import _native as N
 
-__all__ = ["ReducedSGM", "SgmBatch", "CnnTrainer", "SgmError", "default_params", "as_matrix", "load_window_model"]
+__all__ = ["ReducedSGM", "SgmBatch", "CnnTrainer", "Detector", "SgmError", "default_params", "detect_params",
+           "as_matrix", "load_window_model"]
 
 
 class SgmError(RuntimeError):
@@ -53,9 +54,16 @@ def _dev_image(img, device) -> torch.Tensor:
     return img.to(device, non_blocking=True).contiguous()
 
 
-def default_params(width: int, height: int, max_disp: int, **over) -> N.SgmParams:
+def default_params(width: int, height: int, max_disp: int, preset: str = "default", **over) -> N.SgmParams:
+    """Library defaults (preset "default") or the paper's Table 1 settings
+    (preset "paper": census 5x5, P1=6, P2=65), then the overrides."""
     p = N.SgmParams()
-    _check(_lib().sgm_default_params(ctypes.byref(p), width, height, max_disp))
+    if preset == "default":
+        _check(_lib().sgm_default_params(ctypes.byref(p), width, height, max_disp))
+    elif preset == "paper":
+        _check(_lib().sgm_paper_params(ctypes.byref(p), width, height, max_disp))
+    else:
+        raise ValueError(f"unknown preset {preset!r}")
     for k, v in over.items():
         if not hasattr(p, k):
             raise KeyError(k)
@@ -133,6 +141,12 @@ class ReducedSGM:
     def disparity(self) -> torch.Tensor:
         out = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
         _check(_lib().sgm_get_disparity(self._h, _ptr(out), self.W, _stream()))
+        return out
+
+    def disparity_median(self) -> torch.Tensor:
+        """3x3 block median of the filtered disparity (Section 2.3 post-processing)."""
+        out = torch.empty((self.H, self.W), dtype=torch.float32, device=self.device)
+        _check(_lib().sgm_get_disparity_median(self._h, _ptr(out), self.W, _stream()))
         return out
 
     def variance(self) -> torch.Tensor:
@@ -246,6 +260,83 @@ def load_window_model(path: Optional[str] = None) -> np.ndarray:
     if arr.size != N.CNN_NPARAMS:
         raise ValueError(f"{path}: {arr.size} floats, expected {N.CNN_NPARAMS}")
     return arr
+
+
+def detect_params(width: int, height: int, sizes=None, **over) -> N.SgmDetectParams:
+    """Library detection defaults, then the overrides (sizes: list of (w, h))."""
+    p = N.SgmDetectParams()
+    _check(_lib().sgm_detect_default_params(ctypes.byref(p), width, height))
+    if sizes is not None:
+        if not 1 <= len(sizes) <= 8:
+            raise ValueError("1..8 window sizes")
+        p.n_sizes = len(sizes)
+        for k, (w, h) in enumerate(sizes):
+            p.sizes[k][0], p.sizes[k][1] = int(w), int(h)
+    for k, v in over.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+class Detector:
+    """Moving-object boxes from the disagreement of predicted and measured
+    disparity (Section 4); owns a library detector on the current device."""
+
+    def __init__(self, width: int, height: int, sizes=None, device: Optional[torch.device] = None, **params):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.W, self.H = width, height
+        with torch.cuda.device(self.device):
+            self.params = detect_params(width, height, sizes, **params)
+            h = ctypes.c_void_p()
+            _check(_lib().sgm_detector_create(width, height, ctypes.byref(self.params), ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int64()
+        _check(_lib().sgm_detector_windows(self._h, ctypes.byref(n)))
+        self.windows = n.value
+        self.boxes_buf = torch.empty((self.params.max_detections, 4), dtype=torch.int32, device=self.device)
+        self.count_buf = torch.empty(2, dtype=torch.int32, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            with torch.cuda.device(self.device):
+                _lib().sgm_detector_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _result(self):
+        n, fired = (int(v) for v in self.count_buf.cpu())
+        return self.boxes_buf[:n].clone(), fired
+
+    def detect(self, dhat, dz, flags):
+        """Boxes [k, 4] int32 (x0, y0, x1, y1 half-open) and the fired-window count."""
+        dh = torch.as_tensor(dhat).to(self.device, torch.float64).contiguous()
+        z = torch.as_tensor(dz).to(self.device, torch.float64).contiguous()
+        f = torch.as_tensor(flags).to(self.device, torch.uint8).contiguous()
+        _check(_lib().sgm_detect(self._h, _ptr(dh), _ptr(z), _ptr(f), _ptr(self.boxes_buf), _ptr(self.count_buf),
+                                 _stream()))
+        return self._result()
+
+    def detect_frame(self, sgm: "ReducedSGM"):
+        """Boxes of the last frame of a stream."""
+        _check(_lib().sgm_detect_frame(self._h, sgm._h, _ptr(self.boxes_buf), _ptr(self.count_buf), _stream()))
+        return self._result()
+
+    def stage(self, which: int) -> torch.Tensor:
+        top = self.params.top
+        if which == N.DSTAGE_SAT:
+            out = torch.empty((self.H - top + 1, self.W + 1), dtype=torch.int32, device=self.device)
+        elif which == N.DSTAGE_FIRED:
+            out = torch.empty(max(self.windows, 1), dtype=torch.uint8, device=self.device)
+        else:
+            raise ValueError(which)
+        _check(_lib().sgm_detector_stage(self._h, which, _ptr(out), out.numel() * out.element_size(), _stream()))
+        return out[:self.windows] if which == N.DSTAGE_FIRED else out
 
 
 class CnnTrainer:

@@ -23,14 +23,17 @@ STAGE_PATH0 = 16
 (STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX) = range(32, 38)
 
 # every symbol include/sgm.h declares
-EXPORTS = ("sgm_default_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
-           "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_state", "sgm_set_state",
+EXPORTS = ("sgm_default_params", "sgm_paper_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
+           "sgm_get_disparity", "sgm_get_variance", "sgm_get_motion_mask", "sgm_get_disparity_median",
+           "sgm_get_state", "sgm_set_state",
            "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
            "sgm_read_profile", "sgm_batch_create", "sgm_batch_destroy", "sgm_batch_context", "sgm_batch_full",
            "sgm_batch_step", "sgm_batch_step_graph", "sgm_batch_set_schedule", "sgm_batch_autotune",
            "sgm_set_window_model", "sgm_get_features", "sgm_learned_targets", "sgm_cnn_create", "sgm_cnn_destroy",
            "sgm_cnn_set_params", "sgm_cnn_get_params", "sgm_cnn_forward", "sgm_cnn_loss", "sgm_cnn_backward",
-           "sgm_cnn_get_grads", "sgm_cnn_adam", "sgm_cnn_train_step", "sgm_last_error")
+           "sgm_cnn_get_grads", "sgm_cnn_adam", "sgm_cnn_train_step", "sgm_detect_default_params",
+           "sgm_detector_create", "sgm_detector_destroy", "sgm_detector_windows", "sgm_detect", "sgm_detect_frame",
+           "sgm_detector_stage", "sgm_last_error")
 PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta", "cnn", "rerun")
 
 
@@ -43,6 +46,15 @@ class SgmParams(ctypes.Structure):
                 ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
                 ("baseline", ctypes.c_double), ("window_mode", ctypes.c_int32), ("gate_rerun", ctypes.c_int32)]
 
+
+class SgmDetectParams(ctypes.Structure):
+    _fields_ = [("top", ctypes.c_int32), ("n_sizes", ctypes.c_int32), ("sizes", (ctypes.c_int32 * 2) * 8),
+                ("scale", ctypes.c_int32), ("cap", ctypes.c_int32), ("thresh", ctypes.c_int32),
+                ("max_detections", ctypes.c_int32), ("min_area", ctypes.c_int64), ("merge_iou", ctypes.c_double)]
+
+
+DSTAGE_SAT, DSTAGE_FIRED = 0, 1
+DETECT_MAX = 2048
 
 _lib = None
 
@@ -59,6 +71,7 @@ def load(path: str = LIB_PATH):
     P, I32, I64, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
     sig = {
         "sgm_default_params": [ctypes.POINTER(SgmParams), I32, I32, I32],
+        "sgm_paper_params": [ctypes.POINTER(SgmParams), I32, I32, I32],
         "sgm_create": [ctypes.POINTER(SgmParams), ctypes.POINTER(P)],
         "sgm_destroy": [P],
         "sgm_full_frame": [P, P, P, I32, P],
@@ -66,6 +79,7 @@ def load(path: str = LIB_PATH):
         "sgm_get_disparity": [P, P, I32, P],
         "sgm_get_variance": [P, P, I32, P],
         "sgm_get_motion_mask": [P, P, I32, P],
+        "sgm_get_disparity_median": [P, P, I32, P],
         "sgm_get_state": [P, P, P, P, P],
         "sgm_set_state": [P, P, P, P, P],
         "sgm_match_windows": [P, P, P, I32, P, P, P, P, P],
@@ -96,6 +110,13 @@ def load(path: str = LIB_PATH):
         "sgm_cnn_get_grads": [P, ctypes.POINTER(ctypes.c_float), I32],
         "sgm_cnn_adam": [P, ctypes.c_float, P],
         "sgm_cnn_train_step": [P, P, P, I32, ctypes.c_float, P, P],
+        "sgm_detect_default_params": [ctypes.POINTER(SgmDetectParams), I32, I32],
+        "sgm_detector_create": [I32, I32, ctypes.POINTER(SgmDetectParams), P],
+        "sgm_detector_destroy": [P],
+        "sgm_detector_windows": [P, ctypes.POINTER(I64)],
+        "sgm_detect": [P, P, P, P, P, P, P],
+        "sgm_detect_frame": [P, P, P, P, P],
+        "sgm_detector_stage": [P, I32, P, SZ, P],
         "sgm_last_error": [],
     }
     for name, args in sig.items():
@@ -105,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.sgm_destroy.restype = None
     lib.sgm_batch_destroy.restype = None
     lib.sgm_cnn_destroy.restype = None
+    lib.sgm_detector_destroy.restype = None
     lib.sgm_batch_context.restype = ctypes.c_void_p
     lib.sgm_last_error.restype = ctypes.c_char_p
     _lib = lib

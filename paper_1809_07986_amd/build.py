@@ -4,7 +4,8 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = [os.path.join(HERE, "csrc", f) for f in ("sgm_kernels.hip", "sgm_cnn.hip", "sgm_api.hip")]
+SOURCES = [os.path.join(HERE, "csrc", f)
+           for f in ("sgm_kernels.hip", "sgm_cnn.hip", "sgm_detect.hip", "sgm_api.hip")]
 LIB = os.path.join(HERE, "libsgm.so")
 
 HIPCC_FLAGS = [

@@ -358,6 +358,18 @@ int sgm_default_params(sgm_params *out, int32_t width, int32_t height, int32_t m
     return SGM_OK;
 }
 
+int sgm_paper_params(sgm_params *out, int32_t width, int32_t height, int32_t max_disp)
+{
+    int rc = sgm_default_params(out, width, height, max_disp);
+    if (rc)
+        return rc;
+    out->census_w = 5;
+    out->census_h = 5;
+    out->p1 = 6;
+    out->p2 = 65;
+    return SGM_OK;
+}
+
 int sgm_create(const sgm_params *prm, sgm_context **out)
 {
     if (!out)
@@ -629,6 +641,17 @@ int sgm_get_variance(sgm_context *ctx, float *out, int32_t out_pitch, void *stre
         return fail(SGM_EINVAL, "bad output pointer or pitch");
     hipError_t e = launch_state_to_f32(ctx->g, ctx->b.p, out, out_pitch, as_stream(stream));
     return e == hipSuccess ? SGM_OK : hip_fail(e, "conversion launch");
+}
+
+int sgm_get_disparity_median(sgm_context *ctx, float *out, int32_t out_pitch, void *stream)
+{
+    int rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (!out || out_pitch < ctx->g.W)
+        return fail(SGM_EINVAL, "bad output pointer or pitch");
+    hipError_t e = launch_median3x3(ctx->g, ctx->b.d, out, out_pitch, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "median launch");
 }
 
 int sgm_get_motion_mask(sgm_context *ctx, uint8_t *out, int32_t out_pitch, void *stream)
@@ -1416,6 +1439,208 @@ int sgm_cnn_train_step(sgm_cnn *t, const uint16_t *x, const float *targets, int3
     if (rc == SGM_OK)
         rc = sgm_cnn_adam(t, lr, stream);
     return rc;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// moving-object detection
+// ---------------------------------------------------------------------------
+struct sgm_detector {
+    sgm_detect_params prm;
+    DetectGeom dg;
+    int device;
+    int64_t nwin;
+    uint32_t *sat;
+    uint8_t *fire;
+};
+
+namespace {
+
+int check_det(sgm_detector *d)
+{
+    if (!d)
+        return fail(SGM_EINVAL, "detector is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != d->device)
+        return fail(SGM_EINVAL, "detector was created on device %d but device %d is current", d->device, dev);
+    return SGM_OK;
+}
+
+// Validates the settings and fills the window grid; returns the window count
+// or a negative error code.
+int64_t detect_geometry(int32_t W, int32_t H, const sgm_detect_params *p, DetectGeom *dg)
+{
+    if (W < 16 || H < 16 || W > 4096 || (int64_t)W * H > (1 << 24))
+        return fail(SGM_EINVAL, "image size %dx%d outside 16..4096 wide, >= 16 tall, <= 2^24 pixels", W, H);
+    if (p->top < 0 || p->top >= H)
+        return fail(SGM_EINVAL, "top row %d outside [0, %d)", p->top, H);
+    if (p->n_sizes < 1 || p->n_sizes > SGM_DETECT_MAX_SIZES)
+        return fail(SGM_EINVAL, "n_sizes %d outside 1..%d", p->n_sizes, SGM_DETECT_MAX_SIZES);
+    if (p->scale < 1 || p->cap < 1 || p->thresh < 0)
+        return fail(SGM_EINVAL, "need scale >= 1, cap >= 1, thresh >= 0");
+    if (p->max_detections < 1 || p->max_detections > SGM_DETECT_MAX)
+        return fail(SGM_EINVAL, "max_detections %d outside 1..%d", p->max_detections, SGM_DETECT_MAX);
+    if (p->min_area < 0 || !(p->merge_iou >= 0.0 && p->merge_iou <= 1.0))
+        return fail(SGM_EINVAL, "need min_area >= 0 and 0 <= merge_iou <= 1");
+    memset(dg, 0, sizeof(*dg));
+    dg->W = W;
+    dg->H = H;
+    dg->top = p->top;
+    dg->rows = H - p->top;
+    dg->nsizes = p->n_sizes;
+    dg->scale = p->scale;
+    dg->cap = p->cap;
+    dg->thresh = p->thresh;
+    dg->maxdet = p->max_detections;
+    dg->min_area = p->min_area;
+    dg->merge_iou = p->merge_iou;
+    int64_t total = 0;
+    for (int s = 0; s < p->n_sizes; s++) {
+        const int w = p->sizes[s][0], h = p->sizes[s][1];
+        if (w < 1 || h < 1 || w > W || h > H)
+            return fail(SGM_EINVAL, "window %d x %d outside 1..%d x 1..%d", w, h, W, H);
+        if ((uint64_t)w * (uint64_t)h * (uint64_t)p->cap >= (1ull << 32))
+            return fail(SGM_EINVAL, "window %d x %d with cap %d can reach 2^32", w, h, p->cap);
+        dg->w[s] = w;
+        dg->h[s] = h;
+        dg->sx[s] = w / 2 > 0 ? w / 2 : 1;
+        dg->sy[s] = h / 2 > 0 ? h / 2 : 1;
+        dg->nx[s] = (W - w) / dg->sx[s] + 1;
+        const int ny = dg->rows >= h ? (dg->rows - h) / dg->sy[s] + 1 : 0;
+        dg->base[s] = (int)total;
+        total += (int64_t)dg->nx[s] * ny;
+        if (total > (1 << 27))
+            return fail(SGM_EINVAL, "more than 2^27 windows");
+    }
+    dg->base[p->n_sizes] = (int)total;
+    return total;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sgm_detect_default_params(sgm_detect_params *out, int32_t width, int32_t height)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    (void)width;
+    memset(out, 0, sizeof(*out));
+    out->top = height / 3;
+    const int32_t sizes[5][2] = {{20, 20}, {30, 30}, {40, 40}, {50, 50}, {50, 75}};
+    out->n_sizes = 5;
+    memcpy(out->sizes, sizes, sizeof(sizes));
+    out->scale = 16;
+    out->cap = 256;
+    out->thresh = 16;
+    out->max_detections = SGM_DETECT_MAX;
+    out->min_area = 1600;
+    out->merge_iou = 0.0;
+    return SGM_OK;
+}
+
+int sgm_detector_create(int32_t width, int32_t height, const sgm_detect_params *prm, sgm_detector **out)
+{
+    if (!out)
+        return fail(SGM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!prm)
+        return fail(SGM_EINVAL, "params is NULL");
+    DetectGeom dg;
+    int64_t nwin = detect_geometry(width, height, prm, &dg);
+    if (nwin < 0)
+        return (int)nwin;
+    sgm_detector *d = new (std::nothrow) sgm_detector();
+    if (!d)
+        return fail(SGM_ENOMEM, "host allocation failed");
+    d->prm = *prm;
+    d->dg = dg;
+    d->nwin = nwin;
+    d->sat = nullptr;
+    d->fire = nullptr;
+    if (hipGetDevice(&d->device) != hipSuccess) {
+        delete d;
+        return fail(SGM_EHIP, "no HIP device");
+    }
+    hipError_t e = dalloc(&d->sat, (size_t)(dg.rows + 1) * (size_t)(width + 1));
+    if (e == hipSuccess)
+        e = dalloc(&d->fire, (size_t)(nwin > 0 ? nwin : 1));
+    if (e != hipSuccess) {
+        if (d->sat)
+            (void)hipFree(d->sat);
+        if (d->fire)
+            (void)hipFree(d->fire);
+        delete d;
+        return fail(SGM_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    *out = d;
+    return SGM_OK;
+}
+
+void sgm_detector_destroy(sgm_detector *det)
+{
+    if (!det)
+        return;
+    (void)hipFree(det->sat);
+    (void)hipFree(det->fire);
+    delete det;
+}
+
+int sgm_detector_windows(sgm_detector *det, int64_t *n)
+{
+    if (!det || !n)
+        return fail(SGM_EINVAL, "detector or output is NULL");
+    *n = det->nwin;
+    return SGM_OK;
+}
+
+int sgm_detect(sgm_detector *det, const double *dhat, const double *dz, const uint8_t *flags, int32_t *boxes,
+               int32_t *count, void *stream)
+{
+    int rc = check_det(det);
+    if (rc)
+        return rc;
+    if (!dhat || !dz || !flags || !boxes || !count)
+        return fail(SGM_EINVAL, "NULL input or output pointer");
+    hipError_t e = launch_detect(det->dg, dhat, dz, flags, det->sat, det->fire, boxes, count, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "detection launch");
+}
+
+int sgm_detect_frame(sgm_detector *det, sgm_context *ctx, int32_t *boxes, int32_t *count, void *stream)
+{
+    int rc = check_det(det);
+    if (rc == SGM_OK)
+        rc = check_ctx(ctx);
+    if (rc)
+        return rc;
+    if (ctx->g.W != det->dg.W || ctx->g.H != det->dg.H)
+        return fail(SGM_EINVAL, "context is %dx%d, detector %dx%d", ctx->g.W, ctx->g.H, det->dg.W, det->dg.H);
+    return sgm_detect(det, ctx->b.dhat, ctx->b.dz, ctx->b.flags, boxes, count, stream);
+}
+
+int sgm_detector_stage(sgm_detector *det, int32_t stage, void *out, size_t bytes, void *stream)
+{
+    int rc = check_det(det);
+    if (rc)
+        return rc;
+    const void *src = nullptr;
+    size_t need = 0;
+    if (stage == SGM_DSTAGE_SAT) {
+        src = det->sat;
+        need = (size_t)(det->dg.rows + 1) * (size_t)(det->dg.W + 1) * sizeof(uint32_t);
+    } else if (stage == SGM_DSTAGE_FIRED) {
+        src = det->fire;
+        need = (size_t)det->nwin;
+    } else {
+        return fail(SGM_EINVAL, "unknown detector stage %d", stage);
+    }
+    if (!out || bytes < need)
+        return fail(SGM_EINVAL, "stage %d needs %zu bytes", stage, need);
+    if (need == 0)
+        return SGM_OK;
+    hipError_t e = hipMemcpyAsync(out, src, need, hipMemcpyDeviceToDevice, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "stage copy");
 }
 
 }  // extern "C"

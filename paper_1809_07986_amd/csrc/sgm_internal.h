@@ -13,6 +13,8 @@ constexpr int kMaxDisp = 256;          // windows are packed as (lo, width-1) by
 constexpr int kMaxPaths = 8;
 constexpr int kCnnLayers = 5;          // learned window network
 constexpr int kHMaxSeg = 86;           // horizontal aggregation: segments per scanline (>= 4096 / 48)
+constexpr int kDetMaxSizes = 8;         // moving-object detection: window sizes
+constexpr int kDetMaxBoxes = 2048;      // moving-object detection: windows kept for grouping (LDS-resident)
 
 // Device-side layout of one context.  Per-pixel arrays have N = W*H
 // entries in raster order; cost-volume arrays have N*D entries (the worst
@@ -119,5 +121,21 @@ hipError_t launch_windows_to_lohi(const Geometry &g, const DevBuffers &b, int32_
                                   hipStream_t s);
 hipError_t launch_state_to_f32(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);
 hipError_t launch_copy_u8(const Geometry &g, const uint8_t *src, uint8_t *dst, int pitch, hipStream_t s);
+hipError_t launch_median3x3(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);
+
+// moving-object detection: window grid and grouping settings (kernel argument)
+struct DetectGeom {
+    int W, H, top, rows;                // rows = H - top scanned rows
+    int nsizes;
+    int w[kDetMaxSizes], h[kDetMaxSizes];
+    int sx[kDetMaxSizes], sy[kDetMaxSizes];   // window steps
+    int nx[kDetMaxSizes];                     // windows per row of windows
+    int base[kDetMaxSizes + 1];               // first window index of each size; base[nsizes] = total
+    int scale, cap, thresh, maxdet;
+    long long min_area;
+    double merge_iou;
+};
+hipError_t launch_detect(const DetectGeom &dg, const double *dhat, const double *dz, const uint8_t *flags,
+                         uint32_t *sat, uint8_t *fire, int32_t *boxes, int32_t *count, hipStream_t s);
 
 }  // namespace sgmk

@@ -1710,4 +1710,56 @@ hipError_t launch_copy_u8(const Geometry &g, const uint8_t *src, uint8_t *dst, i
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 block median of the filtered disparity (Section 2.3 post-processing,
+// outside the filter loop), clamped borders, written as float32.  The median
+// of 3x3 values: sort each row of three, then the median is the median of
+// (max of the row minima, median of the row medians, min of the row maxima).
+// Every step is a min or max, so the result is one of the nine inputs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void sort3(double &a, double &b, double &c)
+{
+    double lo = fmin(a, b), hi = fmax(a, b);
+    a = fmin(lo, c);
+    double m = fmax(lo, c);
+    b = fmin(hi, m);
+    c = fmax(hi, m);
+}
+
+__device__ __forceinline__ double med3(double a, double b, double c)
+{
+    return fmax(fmin(a, b), fmin(fmax(a, b), c));
+}
+
+__global__ void __launch_bounds__(256) k_median3x3(int W, int H, const double *__restrict__ d,
+                                                   float *__restrict__ out, int pitch)
+{
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (x >= W || y >= H)
+        return;
+    const int xl = x > 0 ? x - 1 : 0, xr = x < W - 1 ? x + 1 : W - 1;
+    double r[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        int yy = min(max(y + i - 1, 0), H - 1);
+        const double *row = d + (size_t)yy * W;
+        r[i][0] = row[xl];
+        r[i][1] = row[x];
+        r[i][2] = row[xr];
+        sort3(r[i][0], r[i][1], r[i][2]);
+    }
+    double lo = fmax(fmax(r[0][0], r[1][0]), r[2][0]);
+    double mid = med3(r[0][1], r[1][1], r[2][1]);
+    double hi = fmin(fmin(r[0][2], r[1][2]), r[2][2]);
+    out[(size_t)y * pitch + x] = (float)med3(lo, mid, hi);
+}
+
+hipError_t launch_median3x3(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_median3x3, dim3((g.W + 63) / 64, (g.H + 3) / 4), dim3(256), 0, s, g.W, g.H, src, dst,
+                       pitch);
+    return hipGetLastError();
+}
+
 }  // namespace sgmk

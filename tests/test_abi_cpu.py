@@ -43,3 +43,18 @@ def test_product_never_touches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "liboracle" not in text and "sgm_oracle" not in text, f
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libsgm.so not built")
+def test_paper_preset_is_table_1():
+    # Table 1, "proposed": P1 6, P2 65, census window 5x5, max disparity 128;
+    # host-only calls (they fill a struct)
+    from paper_1809_07986_amd import _native as N
+    lib = N.load()
+    p, d = N.SgmParams(), N.SgmParams()
+    assert lib.sgm_paper_params(ctypes.byref(p), 1242, 375, 128) == 0
+    assert lib.sgm_default_params(ctypes.byref(d), 1242, 375, 128) == 0
+    assert (p.census_w, p.census_h, p.p1, p.p2, p.max_disp, p.path_mask) == (5, 5, 6, 65, 128, 0xFF)
+    for name, _ in N.SgmParams._fields_:
+        if name not in ("census_w", "census_h", "p1", "p2"):
+            assert getattr(p, name) == getattr(d, name), name

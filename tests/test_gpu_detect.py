@@ -1,0 +1,149 @@
+"""GPU moving-object detection (Section 4) vs the oracle, through the C ABI.
+
+Everything here is integer work once the fixed-point difference is taken
+(both sides take floor(|d^ - d_z| * scale) in double precision), so the
+summed-area table, the fired windows, the boxes and their order are compared
+bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import stereo_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1809_07986_amd as sgmk  # noqa: E402
+from paper_1809_07986_amd import _native as NAT  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _odp(det: "sgmk.Detector") -> O.DetectParams:
+    """The same settings for the oracle, written out from the detector's."""
+    p = det.params
+    return O.DetectParams(sizes=tuple((p.sizes[k][0], p.sizes[k][1]) for k in range(p.n_sizes)), top=p.top,
+                          scale=p.scale, cap=p.cap, thresh=p.thresh, max_detections=p.max_detections,
+                          min_area=p.min_area, merge_iou=p.merge_iou)
+
+
+def _fired_flags(S, dp, H, W):
+    out = []
+    top = H // 3 if dp.top is None else dp.top
+    for (w, h) in dp.sizes:
+        sx, sy = max(w // 2, 1), max(h // 2, 1)
+        for y0 in range(top, H - h + 1, sy):
+            xs = np.arange(0, W - w + 1, sx)
+            s = S[y0 + h, xs + w] - S[y0, xs + w] - S[y0 + h, xs] + S[y0, xs]
+            out.append(s >= dp.thresh * w * h)
+    return np.concatenate(out).astype(np.uint8) if out else np.zeros(0, np.uint8)
+
+
+def _check(det, dhat, dz, flags, label):
+    H, W = dhat.shape
+    dp = _odp(det)
+    want_boxes, want_fired = O.detect(dhat, dz, flags, dp)
+    got_boxes, got_fired = det.detect(dhat, dz, flags)
+    torch.cuda.synchronize()
+    S = O.integral(O.motion_values(dhat, dz, flags, dp.scale, dp.cap))
+    top = dp.top
+    sat = det.stage(NAT.DSTAGE_SAT).cpu().numpy().view(np.uint32)
+    want_sat = ((S[top:] - S[top][None, :]) % (1 << 32)).astype(np.uint32)
+    assert np.array_equal(sat, want_sat), label
+    fired = det.stage(NAT.DSTAGE_FIRED).cpu().numpy()
+    assert np.array_equal(fired, _fired_flags(S, dp, H, W)), label
+    assert got_fired == want_fired, label
+    assert np.array_equal(got_boxes.cpu().numpy(), want_boxes), (label, got_boxes.cpu().numpy(), want_boxes)
+    _say(f"{label}: {want_fired} windows fired, {len(want_boxes)} boxes")
+    return want_boxes
+
+
+def _scene(W, H, rects, diff, seed=0, noise=0.0):
+    rng = np.random.default_rng(seed)
+    dhat = rng.uniform(0, 40, (H, W)) if noise else np.zeros((H, W))
+    dz = dhat + (rng.normal(0, noise, (H, W)) if noise else 0.0)
+    for k, (x0, y0, x1, y1) in enumerate(rects):
+        dz[y0:y1, x0:x1] = dhat[y0:y1, x0:x1] + (diff if np.isscalar(diff) else diff[k])
+    fl = np.full((H, W), O.PRED, np.uint8)
+    return dhat, dz, fl
+
+
+def test_planted_objects():
+    W, H = 400, 180
+    _say("detect planted objects 400x180")
+    det = sgmk.Detector(W, H)
+    dhat, dz, fl = _scene(W, H, [(40, 100, 100, 150), (280, 90, 340, 140), (180, 5, 240, 55)], 5.0)
+    boxes = _check(det, dhat, dz, fl, "planted")
+    assert len(boxes) == 2
+    _check(det, dhat, dhat.copy(), fl, "static")
+    _check(det, dhat, dz, np.zeros_like(fl), "no prediction")
+
+
+@pytest.mark.parametrize("seed,kw", [
+    (1, dict()),
+    (2, dict(merge_iou=0.3, min_area=0)),
+    (3, dict(thresh=4, max_detections=60)),          # more windows fire than are kept
+    (4, dict(sizes=((16, 16), (24, 12), (9, 31)), top=0, min_area=300)),
+    (5, dict(thresh=0, max_detections=400, min_area=0)),   # every window fires
+])
+def test_noisy_scenes(seed, kw):
+    W, H = 333, 170
+    _say(f"detect noisy scene seed={seed} {kw}")
+    rng = np.random.default_rng(seed)
+    rects = []
+    for _ in range(6):
+        x0, y0 = int(rng.integers(0, W - 60)), int(rng.integers(H // 3, H - 30))
+        rects.append((x0, y0, x0 + int(rng.integers(15, 60)), min(H, y0 + int(rng.integers(15, 60)))))
+    diffs = rng.uniform(-6, 6, len(rects))
+    dhat, dz, fl = _scene(W, H, rects, diffs, seed=seed, noise=0.7)
+    fl[rng.random((H, W)) < 0.1] = 0
+    det = sgmk.Detector(W, H, **kw)
+    _check(det, dhat, dz, fl, f"noisy-{seed}")
+
+
+def test_sequence_frames_match_the_oracle_filter():
+    seq = synth.make_sequence("tiny")
+    H, W = seq.cam.height, seq.cam.width
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    F = O.OracleFilter(O.Params(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline))
+    det = sgmk.Detector(W, H, sizes=((12, 12), (20, 20), (24, 36)), min_area=200, thresh=8)
+    dp = _odp(det)
+    for k in range(seq.frames):
+        _say(f"detect tiny frame {k}")
+        if k == 0:
+            g.full_frame(seq.left[0], seq.right[0])
+            F.full_frame(seq.left[0], seq.right[0])
+        else:
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+            F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        got, fired = det.detect_frame(g)
+        torch.cuda.synchronize()
+        if k == 0:
+            assert got.shape[0] == 0 and fired == 0
+            continue
+        assert np.array_equal(g.stage(NAT.STAGE_DZ).cpu().numpy(), F.dz)
+        want, wf = O.detect(F.dhat, F.dz, F.flags, dp)
+        assert fired == wf
+        assert np.array_equal(got.cpu().numpy(), want)
+
+
+def test_invalid_settings_are_rejected():
+    with pytest.raises(sgmk.SgmError):
+        sgmk.Detector(200, 100, top=100)
+    with pytest.raises(sgmk.SgmError):
+        sgmk.Detector(200, 100, max_detections=NAT.DETECT_MAX + 1)
+    with pytest.raises(sgmk.SgmError):
+        sgmk.Detector(200, 100, sizes=((300, 10),))
+    with pytest.raises(sgmk.SgmError):
+        sgmk.Detector(200, 100, cap=1 << 22)     # 50x75 windows could reach 2^32
+    with pytest.raises(sgmk.SgmError):
+        sgmk.Detector(200, 100, merge_iou=-0.1)

@@ -172,10 +172,12 @@ def _compare_state(g, F, label, frame_has_pred):
     _say(f"{label}: state bit-identical={exact}")
 
 
-def _run_sequence(seq, frames, label):
+def _run_sequence(seq, frames, label, preset="default", **kw):
     H, W = seq.cam.height, seq.cam.width
-    g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
-    F = O.OracleFilter(_oracle_params(seq))
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, preset=preset, **_params(seq, **kw))
+    if preset == "paper":   # Table 1: census 5x5, P1 6, P2 65
+        kw = dict(census_w=5, census_h=5, p1=6, p2=65, **kw)
+    F = O.OracleFilter(_oracle_params(seq, **kw))
     for k in range(frames):
         _say(f"case: {label} frame {k}")
         if k == 0:
@@ -193,6 +195,12 @@ def _run_sequence(seq, frames, label):
 def test_free_running_tiny_sequence():
     seq = synth.make_sequence("tiny")
     _run_sequence(seq, seq.frames, "tiny")
+
+
+@pytest.mark.parametrize("mask", [0xFF, 0x0F, 0xF0])
+def test_paper_preset_sequence(mask):
+    seq = synth.make_sequence("tiny")
+    _run_sequence(seq, seq.frames, f"tiny paper preset mask={mask:#x}", preset="paper", path_mask=mask)
 
 
 def test_injected_state_prediction_stage():

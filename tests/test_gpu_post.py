@@ -1,0 +1,78 @@
+"""GPU post-processing vs the oracle: the 3x3 block median (Section 2.3).
+
+The median is one of its nine inputs, so the GPU's float32 output must equal
+the float32 rounding of the oracle's float64 median exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import stereo_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1809_07986_amd as sgmk  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _planted(W, H, seed, kind):
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        d = rng.uniform(0, 127, (H, W))
+    elif kind == "ties":
+        d = rng.integers(0, 4, (H, W)).astype(np.float64) * 0.5
+    else:  # planes with impulses
+        yy, xx = np.mgrid[0:H, 0:W]
+        d = 0.05 * xx + 0.1 * yy
+        m = rng.random((H, W)) < 0.05
+        d[m] = rng.uniform(0, 200, m.sum())
+    return d
+
+
+@pytest.mark.parametrize("W,H,kind", [(16, 16, "uniform"), (67, 19, "ties"), (130, 37, "impulses"),
+                                      (1242, 375, "uniform")])
+def test_median_of_planted_state(W, H, kind):
+    _say(f"median planted {W}x{H} {kind}")
+    d = _planted(W, H, W * 7 + H, kind)
+    p = np.ones((H, W))
+    sf = np.zeros((H, W), np.uint8)
+    g = sgmk.ReducedSGM(W, H, 128)
+    g.set_state(d, p, sf)
+    got = g.disparity_median().cpu().numpy()
+    want = O.median3x3(d).astype(np.float32)
+    assert np.array_equal(got, want)
+    # the state is untouched
+    assert np.array_equal(g.get_state()[0].cpu().numpy(), d)
+
+
+def test_median_after_a_sequence_and_pitch():
+    seq = synth.make_sequence("tiny", frames=4, seed=5)
+    W, H = seq.cam.width, seq.cam.height
+    _say(f"median after sequence {W}x{H}")
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    g.full_frame(seq.left[0], seq.right[0])
+    for k in range(1, 4):
+        g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+    d = g.get_state()[0].cpu().numpy()
+    want = O.median3x3(d).astype(np.float32)
+    assert np.array_equal(g.disparity_median().cpu().numpy(), want)
+    pitch = W + 13
+    out = torch.full((H, pitch), -7.0, dtype=torch.float32, device="cuda")
+    from paper_1809_07986_amd import _native as NAT
+    rc = NAT.load().sgm_get_disparity_median(g._h, out.data_ptr(), pitch, None)
+    assert rc == 0
+    torch.cuda.synchronize()
+    o = out.cpu().numpy()
+    assert np.array_equal(o[:, :W], want)
+    assert np.all(o[:, W:] == -7.0)
+    assert NAT.load().sgm_get_disparity_median(g._h, out.data_ptr(), W - 1, None) != 0
