@@ -226,6 +226,8 @@ def main():
     g.close()
     stage_avg = {k: v / max(nprof, 1) for k, v in stage_ms.items()}
 
+    post = bench_post(seq, Ls, Rs, sched, Ts, params, args.warmup, min(args.steps, 200))
+
     # ---- full-range SGM on the same frames --------------------------------
     full = None
     if not args.skip_full:
@@ -294,6 +296,7 @@ def main():
         "bad_px_gt3": {"reduced_d": round(bad_d / max(nval, 1), 6), "reduced_dz": round(bad_z / max(nval, 1), 6),
                        "full_range": full["bad_px_gt3"] if full else None, "frames": "1-19"},
         "roofline": roofline,
+        "post": post,
     }
     if not args.no_learned:
         out["learned_window"] = bench_learned(args)
@@ -301,6 +304,70 @@ def main():
         cb = cpu_baseline(seq, args.cpu_frames)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(out), flush=True)
+
+
+def _mover_objects(mask: np.ndarray, min_px: int = 400):
+    """Bounding boxes (x0, y0, x1, y1) of the connected moving regions of a frame."""
+    from scipy import ndimage
+    lab, _ = ndimage.label(mask)
+    out = []
+    for k, sl in enumerate(ndimage.find_objects(lab), start=1):
+        if sl is not None and int((lab[sl] == k).sum()) >= min_px:
+            out.append((sl[1].start, sl[0].start, sl[1].stop, sl[0].stop))
+    return out
+
+
+def bench_post(seq, Ls, Rs, sched, Ts, params, warm: int, steps: int):
+    """Section 2.3 median and Section 4 moving-object boxes after each reduced
+    frame (outside the headline step): HIP-event time per call on the stream
+    the library runs on, and how the boxes cover the generator's moving objects."""
+    import torch
+    import paper_1809_07986_amd as sgmk
+    N = sgmk.N
+    lib = N.load()
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    dev = Ls.device
+    g = sgmk.ReducedSGM(W, H, D, **params)
+    det = sgmk.Detector(W, H)
+    g.full_frame(Ls[0], Rs[0])
+    med = torch.empty((H, W), dtype=torch.float32, device=dev)
+    boxes = torch.empty((det.params.max_detections, 4), dtype=torch.int32, device=dev)
+    count = torch.empty(2, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    hit, objs, boxes_total, fp = 0, 0, 0, 0
+    ev = []
+    for i in range(warm + steps):
+        a, b = sched[i]
+        g.reduced_frame(Ls[b], Rs[b], Ts[i])
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        sgmk._check(lib.sgm_get_disparity_median(g._h, med.data_ptr(), W, stream.cuda_stream))
+        e1.record(stream)
+        sgmk._check(lib.sgm_detect_frame(det._h, g._h, boxes.data_ptr(), count.data_ptr(), stream.cuda_stream))
+        e2.record(stream)
+        if i >= warm:
+            ev.append((e0, e1, e2))
+        if i < seq.frames - 1:     # first sweep: coverage of the moving objects of frame b
+            n = int(count[0].item())
+            bx = boxes[:n].cpu().numpy()
+            boxes_total += n
+            gt = _mover_objects(seq.mover[b])
+            objs += len(gt)
+            for (x0, y0, x1, y1) in gt:
+                hit += any(bx[j, 0] < x1 and x0 < bx[j, 2] and bx[j, 1] < y1 and y0 < bx[j, 3] for j in range(n))
+            for j in range(n):
+                fp += not any(bx[j, 0] < x1 and x0 < bx[j, 2] and bx[j, 1] < y1 and y0 < bx[j, 3]
+                              for (x0, y0, x1, y1) in gt)
+    torch.cuda.synchronize()
+    med_ms = float(np.mean([e0.elapsed_time(e1) for e0, e1, _ in ev]))
+    det_ms = float(np.mean([e1.elapsed_time(e2) for _, e1, e2 in ev]))
+    g.close()
+    det.close()
+    return {"median3x3_ms": round(med_ms, 5), "detect_ms": round(det_ms, 5), "frames_timed": len(ev),
+            "detect_windows_per_frame": det.windows,
+            "median_gbs": round(H * W * 12 / (med_ms * 1e-3) / 1e9, 1),
+            "moving_objects_hit": f"{hit}/{objs}", "boxes": boxes_total, "boxes_on_static_scene": fp,
+            "coverage_frames": "1-19, objects of >= 400 px"}
 
 
 def bench_learned(args):

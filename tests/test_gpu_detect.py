@@ -147,3 +147,28 @@ def test_invalid_settings_are_rejected():
         sgmk.Detector(200, 100, cap=1 << 22)     # 50x75 windows could reach 2^32
     with pytest.raises(sgmk.SgmError):
         sgmk.Detector(200, 100, merge_iou=-0.1)
+
+
+def test_driving_frames_full_size():
+    # 1242x375 with the default detector (all five window sizes), four
+    # reduced frames of the oracle filter and of the library side by side
+    seq = synth.make_sequence("driving", frames=5)
+    H, W = seq.cam.height, seq.cam.width
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    F = O.OracleFilter(O.Params(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline))
+    det = sgmk.Detector(W, H)
+    dp = _odp(det)
+    g.full_frame(seq.left[0], seq.right[0])
+    F.full_frame(seq.left[0], seq.right[0])
+    for k in range(1, seq.frames):
+        _say(f"detect driving frame {k}")
+        g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        got, fired = det.detect_frame(g)
+        torch.cuda.synchronize()
+        assert np.array_equal(g.stage(NAT.STAGE_DZ).cpu().numpy(), F.dz)
+        assert np.array_equal(g.stage(NAT.STAGE_DHAT).cpu().numpy(), F.dhat)
+        want, wf = O.detect(F.dhat, F.dz, F.flags, dp)
+        assert fired == wf
+        assert np.array_equal(got.cpu().numpy(), want)
+        _say(f"  {wf} windows fired, boxes {want.tolist()}")

@@ -76,3 +76,25 @@ def test_median_after_a_sequence_and_pitch():
     assert np.array_equal(o[:, :W], want)
     assert np.all(o[:, W:] == -7.0)
     assert NAT.load().sgm_get_disparity_median(g._h, out.data_ptr(), W - 1, None) != 0
+
+
+def test_process_noise_errors_match_the_oracle_prediction():
+    # Section 3: the ground truth of frame k-1 warped to frame k; the tool's
+    # errors equal those of the oracle's prediction of the same state
+    from paper_1809_07986_amd import _native as NAT
+    from paper_1809_07986_amd.estimate_noise import RESET, process_errors
+    seq = synth.make_sequence("tiny")
+    W, H = seq.cam.width, seq.cam.height
+    _say("process-noise errors, tiny sequence")
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    prm = O.Params(W, H, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+    for k in range(1, seq.frames):
+        got = process_errors(g, seq, k, seq.T[k], torch, NAT)
+        v0 = seq.valid[k - 1]
+        d = np.where(v0, seq.disp_gt[k - 1].astype(np.float64), 0.0)
+        sf = np.where(v0, 0, RESET).astype(np.uint8)
+        dhat, _, fl, _, _ = O.predict(prm, d, np.ones_like(d), sf, seq.T[k])
+        use = ((fl & O.PRED) > 0) & ((fl & O.RESET) == 0) & seq.valid[k] & ~seq.mover[k] & ~seq.mover[k - 1]
+        want = (dhat - seq.disp_gt[k].astype(np.float64))[use]
+        assert got.size == want.size > 100
+        assert np.array_equal(got, want)
