@@ -1451,6 +1451,7 @@ struct sgm_detector {
     DetectGeom dg;
     int device;
     int64_t nwin;
+    uint32_t *colp;   // column prefixes of the difference values, rows x width
     uint32_t *sat;
     uint8_t *fire;
 };
@@ -1557,6 +1558,7 @@ int sgm_detector_create(int32_t width, int32_t height, const sgm_detect_params *
     d->prm = *prm;
     d->dg = dg;
     d->nwin = nwin;
+    d->colp = nullptr;
     d->sat = nullptr;
     d->fire = nullptr;
     if (hipGetDevice(&d->device) != hipSuccess) {
@@ -1565,8 +1567,12 @@ int sgm_detector_create(int32_t width, int32_t height, const sgm_detect_params *
     }
     hipError_t e = dalloc(&d->sat, (size_t)(dg.rows + 1) * (size_t)(width + 1));
     if (e == hipSuccess)
+        e = dalloc(&d->colp, (size_t)dg.rows * (size_t)width);
+    if (e == hipSuccess)
         e = dalloc(&d->fire, (size_t)(nwin > 0 ? nwin : 1));
     if (e != hipSuccess) {
+        if (d->colp)
+            (void)hipFree(d->colp);
         if (d->sat)
             (void)hipFree(d->sat);
         if (d->fire)
@@ -1582,6 +1588,7 @@ void sgm_detector_destroy(sgm_detector *det)
 {
     if (!det)
         return;
+    (void)hipFree(det->colp);
     (void)hipFree(det->sat);
     (void)hipFree(det->fire);
     delete det;
@@ -1603,7 +1610,8 @@ int sgm_detect(sgm_detector *det, const double *dhat, const double *dz, const ui
         return rc;
     if (!dhat || !dz || !flags || !boxes || !count)
         return fail(SGM_EINVAL, "NULL input or output pointer");
-    hipError_t e = launch_detect(det->dg, dhat, dz, flags, det->sat, det->fire, boxes, count, as_stream(stream));
+    hipError_t e = launch_detect(det->dg, dhat, dz, flags, det->colp, det->sat, det->fire, boxes, count,
+                                 as_stream(stream));
     return e == hipSuccess ? SGM_OK : hip_fail(e, "detection launch");
 }
 

@@ -9,13 +9,15 @@
 // by its bounding box, then boxes below the minimum area are dropped.
 //
 // Kernels (one launch each, in stream order):
-//   k_det_rows    one workgroup per scanned row: difference values and the
-//                 inclusive prefix along the row (row r+1 of the table).
-//   k_det_cols    one thread per table column: prefix down the rows.
+//   k_det_cols    64 columns x 16 row chunks per workgroup: difference
+//                 values and their prefix down the scanned rows.
+//   k_det_rows    one workgroup per scanned row: prefix of the column
+//                 prefixes along the row (row r+1 of the table).
 //   k_det_windows one thread per window: fired / not fired.
 //   k_det_group   one workgroup of 1024 threads: ordered compaction of the
-//                 fired windows, greedy grouping with a cached best partner
-//                 per box, minimum-area filter, output.
+//                 fired windows, split into independent groups, greedy
+//                 grouping with one wave per group, minimum-area filter,
+//                 output.
 //
 // The table holds uint32 sums that may wrap: a window sum is the
 // inclusion-exclusion of four entries modulo 2^32, exact because the host
@@ -118,45 +120,73 @@ __device__ __forceinline__ void wave_best(int &I, int &U, int &idx)
 
 }  // namespace
 
-__global__ void __launch_bounds__(256) k_det_rows(DetectGeom dg, const double *__restrict__ dhat,
-                                                  const double *__restrict__ dz, const uint8_t *__restrict__ flags,
+// Column prefix of the difference values over the scanned rows.  A
+// workgroup takes 64 columns (one per lane) and splits the rows into 16
+// chunks (one per wave): each thread sums its chunk, the chunk sums are
+// scanned through LDS, and each thread then writes the running prefix of its
+// chunk (the inputs are read twice; the second read hits the cache).
+constexpr int kColTile = 64, kColChunks = 16;
+
+__device__ __forceinline__ uint32_t diff_value(const DetectGeom &dg, const double *__restrict__ dhat,
+                                               const double *__restrict__ dz, const uint8_t *__restrict__ flags,
+                                               int y, int x)
+{
+    const size_t i = (size_t)y * dg.W + x;
+    const double dh = dhat[i];
+    if ((flags[i] & SGM_FLAG_PRED) && (double)x - dh >= 0.0)
+        return (uint32_t)fmin(floor(fabs(dh - dz[i]) * (double)dg.scale), (double)dg.cap);
+    return 0;
+}
+
+__global__ void __launch_bounds__(1024) k_det_cols(DetectGeom dg, const double *__restrict__ dhat,
+                                                   const double *__restrict__ dz, const uint8_t *__restrict__ flags,
+                                                   uint32_t *__restrict__ colp)
+{
+    __shared__ uint32_t part[kColChunks][kColTile];
+    const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+    const int x = blockIdx.x * kColTile + lane;
+    const int per = (dg.rows + kColChunks - 1) / kColChunks;
+    const int r0 = min(c * per, dg.rows), r1 = min(r0 + per, dg.rows);
+    uint32_t sum = 0;
+    if (x < dg.W)
+        for (int r = r0; r < r1; r++)
+            sum += diff_value(dg, dhat, dz, flags, dg.top + r, x);
+    part[c][lane] = sum;
+    __syncthreads();
+    uint32_t acc = 0;
+    for (int k = 0; k < c; k++)
+        acc += part[k][lane];
+    if (x < dg.W)
+        for (int r = r0; r < r1; r++) {
+            acc += diff_value(dg, dhat, dz, flags, dg.top + r, x);
+            colp[(size_t)r * dg.W + x] = acc;
+        }
+}
+
+// Row r+1 of the summed-area table: inclusive prefix of the column prefixes
+// along row r (one workgroup per row; block 0 also writes the zero row).
+__global__ void __launch_bounds__(256) k_det_rows(DetectGeom dg, const uint32_t *__restrict__ colp,
                                                   uint32_t *__restrict__ sat)
 {
     __shared__ int lds[16];
-    const int r = blockIdx.x, y = dg.top + r;
+    const int r = blockIdx.x;
     const size_t stride = (size_t)dg.W + 1;
     uint32_t *row = sat + (size_t)(r + 1) * stride;
+    const uint32_t *src = colp + (size_t)r * dg.W;
+    if (r == 0)
+        for (int x = threadIdx.x; x <= dg.W; x += 256)
+            sat[x] = 0;
     if (threadIdx.x == 0)
         row[0] = 0;
     int carry = 0;
     for (int x0 = 0; x0 < dg.W; x0 += 256) {
         const int x = x0 + threadIdx.x;
-        int v = 0;
-        if (x < dg.W) {
-            const size_t i = (size_t)y * dg.W + x;
-            const double dh = dhat[i];
-            if ((flags[i] & SGM_FLAG_PRED) && (double)x - dh >= 0.0)
-                v = (int)fmin(floor(fabs(dh - dz[i]) * (double)dg.scale), (double)dg.cap);
-        }
+        const int v = x < dg.W ? (int)src[x] : 0;
         int total;
-        int ex = block_excl_scan(v, lds, &total);
+        const int ex = block_excl_scan(v, lds, &total);   // wrapping int sums: exact modulo 2^32
         if (x < dg.W)
             row[x + 1] = (uint32_t)(carry + ex + v);
         carry += total;
-    }
-}
-
-__global__ void __launch_bounds__(256) k_det_cols(DetectGeom dg, uint32_t *__restrict__ sat)
-{
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    if (x > dg.W)
-        return;
-    const size_t stride = (size_t)dg.W + 1;
-    sat[x] = 0;
-    uint32_t acc = 0;
-    for (int r = 1; r <= dg.rows; r++) {
-        acc += sat[(size_t)r * stride + x];
-        sat[(size_t)r * stride + x] = acc;
     }
 }
 
@@ -174,23 +204,148 @@ __global__ void __launch_bounds__(256) k_det_windows(DetectGeom dg, const uint32
     fire[t] = (uint64_t)sum >= (uint64_t)dg.thresh * (uint64_t)(w * h) ? 1 : 0;
 }
 
+namespace {
+
+// Union-find over box indices in LDS: parents only point to smaller
+// indices, so every set ends with its smallest index as the root.
+// Path halving: a non-root points to its grandparent (an ancestor, so
+// concurrent walks still end at the root; roots are only written by the
+// hooking compare-and-swap).
+__device__ int uf_find(volatile int *par, int x)
+{
+    for (;;) {
+        const int p = par[x];
+        if (p == x)
+            return x;
+        const int gp = par[p];
+        if (gp == p)
+            return p;
+        par[x] = gp;
+        x = gp;
+    }
+}
+
+// pair index p of the strictly lower triangle -> (a, b), a > b >= 0
+__device__ __forceinline__ void tri_pair(int p, int &a, int &b)
+{
+    int r = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+    while ((long long)r * (r - 1) / 2 > p)
+        r--;
+    while ((long long)(r + 1) * r / 2 <= p)
+        r++;
+    a = r;
+    b = p - (int)((long long)r * (r - 1) / 2);
+}
+
+__device__ void uf_unite(int *par, int a, int b)
+{
+    for (;;) {
+        a = uf_find(par, a);
+        b = uf_find(par, b);
+        if (a == b)
+            return;
+        if (a > b) {
+            int t = a;
+            a = b;
+            b = t;
+        }
+        if (atomicCAS(&par[b], b, a) == b)
+            return;
+    }
+}
+
+__device__ __forceinline__ bool overlap(const Box &a, const Box &b)
+{
+    return min(a.x1, b.x1) > max(a.x0, b.x0) && min(a.y1, b.y1) > max(a.y0, b.y0);
+}
+
+// orders this wave's LDS writes before its later LDS reads (all lanes)
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void wave_minmax(Box &b)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        b.x0 = min(b.x0, __shfl_xor(b.x0, o, 64));
+        b.y0 = min(b.y0, __shfl_xor(b.y0, o, 64));
+        b.x1 = max(b.x1, __shfl_xor(b.x1, o, 64));
+        b.y1 = max(b.y1, __shfl_xor(b.y1, o, 64));
+    }
+}
+
+// best partner of box a among the members of its group (wave-wide; every
+// lane returns the same result)
+__device__ void group_best(const short4 *bx, const uint8_t *alive, const short *mem, int st, int m, int a, int &BI,
+                           int &BU, int &BJ)
+{
+    const int lane = threadIdx.x & 63;
+    const Box A = get_box(bx, a);
+    const int aa = area(A);
+    BI = -1;
+    BU = 1;
+    BJ = INT_MAX;
+    for (int q = lane; q < m; q += 64) {
+        const int b = mem[st + q];
+        if (b == a || !alive[b])
+            continue;
+        const Box B = get_box(bx, b);
+        const int I = inter(A, B), U = aa + area(B) - I;
+        if (ranks_before(I, U, b, BI, BU, BJ)) {
+            BI = I;
+            BU = U;
+            BJ = b;
+        }
+    }
+    wave_best(BI, BU, BJ);
+}
+
+}  // namespace
+
+// LDS layout of k_det_group (bytes per box slot): bx 8, bI 4, bU 4, bj 2,
+// par 4, mem 2, gs 4, gl 4, fl 4, alive 1.
+constexpr size_t kDetGroupLds = (size_t)kDetMaxBoxes * 37;
+
+// Ordered compaction of the fired windows, then the greedy grouping.
+//
+// Boxes that never overlap never merge (IoU 0 does not exceed a threshold
+// >= 0), and a merged box stays inside the bounding box of the boxes it came
+// from.  So the boxes are first split into groups: connected sets of
+// overlapping boxes, joined further while the bounding boxes of two groups
+// overlap.  No box of one group can ever overlap a box of another, and the
+// greedy sequence inside a group does not depend on the others: each wave
+// runs the grouping of one group at a time with wave-level synchronisation
+// only, and all groups run in parallel.  Within a group every box keeps its
+// best partner (highest IoU, then the lowest index); after a merge only the
+// boxes whose partner was one of the pair search again, the others compare
+// their partner with the merged box.
 __global__ void __launch_bounds__(1024) k_det_group(DetectGeom dg, const uint8_t *__restrict__ fire,
                                                     int32_t *__restrict__ out, int32_t *__restrict__ count)
 {
-    __shared__ short4 bx[kDetMaxBoxes];
-    __shared__ int bI[kDetMaxBoxes], bU[kDetMaxBoxes];
-    __shared__ short bj[kDetMaxBoxes];
-    __shared__ uint8_t alive[kDetMaxBoxes];
-    __shared__ short flagged[kDetMaxBoxes];
+    extern __shared__ __align__(16) unsigned char smem[];
+    short4 *bx = (short4 *)smem;
+    int *bI = (int *)(bx + kDetMaxBoxes);
+    int *bU = bI + kDetMaxBoxes;
+    short *bj = (short *)(bU + kDetMaxBoxes);
+    int *par = (int *)(bj + kDetMaxBoxes);
+    short *mem = (short *)(par + kDetMaxBoxes);
+    int *gs = (int *)(mem + kDetMaxBoxes);
+    int *gl = gs + kDetMaxBoxes;
+    int *fl = gl + kDetMaxBoxes;
+    uint8_t *alive = (uint8_t *)(fl + kDetMaxBoxes);
+    short4 *gbox = (short4 *)bI;   // group boxes while grouping (bI, bU unused then)
+    short *roots = bj;             // group roots while grouping (bj unused then)
     __shared__ int lds[16];
-    __shared__ int redI[16], redU[16], redX[16];
-    __shared__ int sel[3];
-    __shared__ int nflag;
+    __shared__ int nroots, changed;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nwin = dg.base[dg.nsizes];
 
-    // ordered compaction of the fired windows (window order = size, row, column)
+    // ---- ordered compaction (window order = size, row, column) ----------
     const int chunk = (nwin + 1023) / 1024;
     const int c0 = min(tid * chunk, nwin), c1 = min(c0 + chunk, nwin);
     int mine = 0;
@@ -210,128 +365,209 @@ __global__ void __launch_bounds__(1024) k_det_group(DetectGeom dg, const uint8_t
         }
     }
     const int n = min(fired, dg.maxdet);
-    for (int i = tid; i < n; i += 1024)
-        alive[i] = 1;
-    __syncthreads();
-
-    // best partner of every box: highest IoU, then the lowest index
     for (int i = tid; i < n; i += 1024) {
-        const Box a = get_box(bx, i);
-        const int aa = area(a);
-        int BI = -1, BU = 1, BJ = INT_MAX;
-        for (int j = 0; j < n; j++) {
-            if (j == i)
-                continue;
-            const Box b = get_box(bx, j);
-            const int I = inter(a, b), U = aa + area(b) - I;
-            if (ranks_before(I, U, j, BI, BU, BJ)) {
-                BI = I;
-                BU = U;
-                BJ = j;
-            }
-        }
-        bI[i] = BI;
-        bU[i] = BU;
-        bj[i] = BJ == INT_MAX ? (short)-1 : (short)BJ;
+        alive[i] = 1;
+        par[i] = i;
     }
     __syncthreads();
 
+    // ---- groups: overlapping boxes, then overlapping group boxes ---------
+    const int npairs = n * (n - 1) / 2;
+    for (int p = tid; p < npairs; p += 1024) {
+        int i, j;
+        tri_pair(p, i, j);
+        if (overlap(get_box(bx, i), get_box(bx, j)))
+            uf_unite(par, i, j);
+    }
+    __syncthreads();
+    const int nchunk = (n + 1023) / 1024;
+    const int i0 = min(tid * nchunk, n), i1 = min(i0 + nchunk, n);
     for (;;) {
-        // the pair with the highest IoU: the best box, then its partner
-        int I = -1, U = 1, X = INT_MAX;
         for (int i = tid; i < n; i += 1024) {
-            if (alive[i] && bj[i] >= 0 && ranks_before(bI[i], bU[i], i, I, U, X)) {
-                I = bI[i];
-                U = bU[i];
-                X = i;
-            }
-        }
-        wave_best(I, U, X);
-        if (lane == 0) {
-            redI[wave] = I;
-            redU[wave] = U;
-            redX[wave] = X;
+            par[i] = uf_find(par, i);
+            gl[i] = 0;
         }
         __syncthreads();
-        if (wave == 0) {
-            I = lane < 16 ? redI[lane] : -1;
-            U = lane < 16 ? redU[lane] : 1;
-            X = lane < 16 ? redX[lane] : INT_MAX;
-            wave_best(I, U, X);
-            if (lane == 0) {
-                sel[0] = I;
-                sel[1] = U;
-                sel[2] = X;
-                nflag = 0;
-            }
-        }
+        for (int i = tid; i < n; i += 1024)
+            atomicAdd(&gl[par[i]], 1);
         __syncthreads();
-        const int si = sel[2];
-        if (si == INT_MAX || !((double)sel[0] > dg.merge_iou * (double)sel[1]))
-            break;
-        const int sj = bj[si];
-        const Box A = get_box(bx, si), B = get_box(bx, sj);
-        const Box m{min(A.x0, B.x0), min(A.y0, B.y0), max(A.x1, B.x1), max(A.y1, B.y1)};
-        const int am = area(m);
-        // boxes whose partner was one of the pair search again; the others
-        // only compare the merged box with their current partner
-        for (int k = tid; k < n; k += 1024) {
-            if (!alive[k] || k == sj)
-                continue;
-            if (k == si || bj[k] == si || bj[k] == sj) {
-                flagged[atomicAdd(&nflag, 1)] = (short)k;
-                continue;
+        // roots in ascending order and the start of each group's member list
+        int nr = 0, nm = 0;
+        for (int i = i0; i < i1; i++)
+            if (par[i] == i) {
+                nr++;
+                nm += gl[i];
             }
-            const Box b = get_box(bx, k);
-            const int Ik = inter(b, m), Uk = area(b) + am - Ik;
-            if (ranks_before(Ik, Uk, si, bI[k], bU[k], bj[k])) {
-                bI[k] = Ik;
-                bU[k] = Uk;
-                bj[k] = (short)si;
+        int tr, tm;
+        int gr = block_excl_scan(nr, lds, &tr);
+        int gm = block_excl_scan(nm, lds, &tm);
+        for (int i = i0; i < i1; i++)
+            if (par[i] == i) {
+                roots[gr++] = (short)i;
+                gs[i] = gm;
+                fl[i] = gm;
+                gm += gl[i];
             }
-        }
-        __syncthreads();
         if (tid == 0) {
-            bx[si] = make_short4((short)m.x0, (short)m.y0, (short)m.x1, (short)m.y1);
-            alive[sj] = 0;
+            nroots = tr;
+            changed = 0;
         }
         __syncthreads();
-        const int nf = nflag;
-        for (int f = wave; f < nf; f += 16) {
-            const int k = flagged[f];
-            const Box a = get_box(bx, k);
-            const int aa = area(a);
-            int BI = -1, BU = 1, BJ = INT_MAX;
-            for (int j = lane; j < n; j += 64) {
-                if (j == k || !alive[j])
-                    continue;
-                const Box b = get_box(bx, j);
-                const int Ij = inter(a, b), Uj = aa + area(b) - Ij;
-                if (ranks_before(Ij, Uj, j, BI, BU, BJ)) {
-                    BI = Ij;
-                    BU = Uj;
-                    BJ = j;
+        for (int i = tid; i < n; i += 1024)
+            mem[atomicAdd(&fl[par[i]], 1)] = (short)i;
+        __syncthreads();
+        const int r = nroots;
+        for (int g = wave; g < r; g += 16) {
+            const int root = roots[g], st = gs[root], m = gl[root];
+            Box b{INT_MAX, INT_MAX, INT_MIN, INT_MIN};
+            for (int q = lane; q < m; q += 64) {
+                const Box c = get_box(bx, mem[st + q]);
+                b.x0 = min(b.x0, c.x0);
+                b.y0 = min(b.y0, c.y0);
+                b.x1 = max(b.x1, c.x1);
+                b.y1 = max(b.y1, c.y1);
+            }
+            wave_minmax(b);
+            if (lane == 0)
+                gbox[g] = make_short4((short)b.x0, (short)b.y0, (short)b.x1, (short)b.y1);
+        }
+        __syncthreads();
+        const int rpairs = r * (r - 1) / 2;
+        for (int p = tid; p < rpairs; p += 1024) {
+            int g, h;
+            tri_pair(p, g, h);
+            if (overlap(get_box(gbox, g), get_box(gbox, h))) {
+                uf_unite(par, roots[g], roots[h]);
+                changed = 1;
+            }
+        }
+        __syncthreads();
+        if (!changed)
+            break;
+        __syncthreads();
+    }
+    const int r = nroots;
+    if (dg.merge_iou == 0.0) {
+        // Merging while any two boxes overlap ends in one box per group:
+        // inside a group every merge keeps the overlap graph connected, so
+        // the group collapses to its bounding box, and the groups are the
+        // finest split whose bounding boxes do not overlap, which is the
+        // end state of every merge order.  The merged box sits at the
+        // group's smallest index, its root.
+        for (int g = tid; g < r; g += 1024)
+            bx[roots[g]] = gbox[g];
+        for (int i = tid; i < n; i += 1024)
+            alive[i] = par[i] == i;
+        __syncthreads();
+    }
+    // per group index: start and size of the member list
+    const int rg = dg.merge_iou == 0.0 ? 0 : r;
+    int ga_st = 0, ga_m = 0, gb_st = 0, gb_m = 0;
+    if (tid < rg) {
+        ga_st = gs[roots[tid]];
+        ga_m = gl[roots[tid]];
+    }
+    if (tid + 1024 < rg) {
+        gb_st = gs[roots[tid + 1024]];
+        gb_m = gl[roots[tid + 1024]];
+    }
+    __syncthreads();
+    if (tid < rg) {
+        gs[tid] = ga_st;
+        gl[tid] = ga_m;
+    }
+    if (tid + 1024 < rg) {
+        gs[tid + 1024] = gb_st;
+        gl[tid + 1024] = gb_m;
+    }
+    __syncthreads();
+
+    // ---- greedy grouping, one wave per group -----------------------------
+    for (int g = wave; g < rg; g += 16) {
+        const int st = gs[g], m = gl[g];
+        if (m < 2)
+            continue;
+        for (int q = 0; q < m; q++) {
+            const int a = mem[st + q];
+            int BI, BU, BJ;
+            group_best(bx, alive, mem, st, m, a, BI, BU, BJ);
+            if (lane == 0) {
+                bI[a] = BI;
+                bU[a] = BU;
+                bj[a] = BJ == INT_MAX ? (short)-1 : (short)BJ;
+            }
+        }
+        wave_sync();
+        for (;;) {
+            int I = -1, U = 1, X = INT_MAX;
+            for (int q = lane; q < m; q += 64) {
+                const int a = mem[st + q];
+                if (alive[a] && bj[a] >= 0 && ranks_before(bI[a], bU[a], a, I, U, X)) {
+                    I = bI[a];
+                    U = bU[a];
+                    X = a;
                 }
             }
-            wave_best(BI, BU, BJ);
-            if (lane == 0) {
-                bI[k] = BI;
-                bU[k] = BU;
-                bj[k] = BJ == INT_MAX ? (short)-1 : (short)BJ;
+            wave_best(I, U, X);
+            if (X == INT_MAX || !((double)I > dg.merge_iou * (double)U))
+                break;
+            const int si = X, sj = bj[si];
+            const Box A = get_box(bx, si), B = get_box(bx, sj);
+            const Box mb{min(A.x0, B.x0), min(A.y0, B.y0), max(A.x1, B.x1), max(A.y1, B.y1)};
+            const int am = area(mb);
+            int nflag = 0;
+            for (int q0 = 0; q0 < m; q0 += 64) {
+                const int q = q0 + lane;
+                bool flag = false;
+                if (q < m) {
+                    const int k = mem[st + q];
+                    if (alive[k] && k != sj) {
+                        if (k == si || bj[k] == si || bj[k] == sj) {
+                            flag = true;
+                        } else {
+                            const Box b = get_box(bx, k);
+                            const int Ik = inter(b, mb), Uk = area(b) + am - Ik;
+                            if (ranks_before(Ik, Uk, si, bI[k], bU[k], bj[k])) {
+                                bI[k] = Ik;
+                                bU[k] = Uk;
+                                bj[k] = (short)si;
+                            }
+                        }
+                    }
+                }
+                const unsigned long long mask = __ballot(flag);
+                if (flag)
+                    fl[st + nflag + __popcll(mask & ((1ull << lane) - 1ull))] = mem[st + q];
+                nflag += __popcll(mask);
             }
+            wave_sync();
+            if (lane == 0) {
+                bx[si] = make_short4((short)mb.x0, (short)mb.y0, (short)mb.x1, (short)mb.y1);
+                alive[sj] = 0;
+            }
+            wave_sync();
+            for (int f = 0; f < nflag; f++) {
+                const int k = fl[st + f];
+                int BI, BU, BJ;
+                group_best(bx, alive, mem, st, m, k, BI, BU, BJ);
+                if (lane == 0) {
+                    bI[k] = BI;
+                    bU[k] = BU;
+                    bj[k] = BJ == INT_MAX ? (short)-1 : (short)BJ;
+                }
+            }
+            wave_sync();
         }
-        __syncthreads();
     }
+    __syncthreads();
 
-    // drop boxes below the minimum area, keep list order
-    const int ch2 = (n + 1023) / 1024;
-    const int d0 = min(tid * ch2, n), d1 = min(d0 + ch2, n);
+    // ---- drop boxes below the minimum area, keep list order -------------
     int keep = 0;
-    for (int i = d0; i < d1; i++)
+    for (int i = i0; i < i1; i++)
         keep += alive[i] && (long long)area(get_box(bx, i)) >= dg.min_area;
     int kept;
     int o = block_excl_scan(keep, lds, &kept);
-    for (int i = d0; i < d1; i++) {
+    for (int i = i0; i < i1; i++) {
         if (alive[i]) {
             const Box b = get_box(bx, i);
             if ((long long)area(b) >= dg.min_area) {
@@ -350,15 +586,28 @@ __global__ void __launch_bounds__(1024) k_det_group(DetectGeom dg, const uint8_t
 }
 
 hipError_t launch_detect(const DetectGeom &dg, const double *dhat, const double *dz, const uint8_t *flags,
-                         uint32_t *sat, uint8_t *fire, int32_t *boxes, int32_t *count, hipStream_t s)
+                         uint32_t *colp, uint32_t *sat, uint8_t *fire, int32_t *boxes, int32_t *count, hipStream_t s)
 {
-    if (dg.rows > 0)
-        hipLaunchKernelGGL(k_det_rows, dim3(dg.rows), dim3(256), 0, s, dg, dhat, dz, flags, sat);
-    hipLaunchKernelGGL(k_det_cols, dim3((dg.W + 1 + 255) / 256), dim3(256), 0, s, dg, sat);
+    static bool lds_ok[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= 64 || !lds_ok[dev]) {
+        e = hipFuncSetAttribute((const void *)k_det_group, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)kDetGroupLds);
+        if (e != hipSuccess)
+            return e;
+        if (dev >= 0 && dev < 64)
+            lds_ok[dev] = true;
+    }
+    hipLaunchKernelGGL(k_det_cols, dim3((dg.W + kColTile - 1) / kColTile), dim3(1024), 0, s, dg, dhat, dz, flags,
+                       colp);
+    hipLaunchKernelGGL(k_det_rows, dim3(dg.rows), dim3(256), 0, s, dg, colp, sat);
     const int nwin = dg.base[dg.nsizes];
     if (nwin > 0)
         hipLaunchKernelGGL(k_det_windows, dim3((nwin + 255) / 256), dim3(256), 0, s, dg, sat, fire);
-    hipLaunchKernelGGL(k_det_group, dim3(1), dim3(1024), 0, s, dg, fire, boxes, count);
+    hipLaunchKernelGGL(k_det_group, dim3(1), dim3(1024), kDetGroupLds, s, dg, fire, boxes, count);
     return hipGetLastError();
 }
 

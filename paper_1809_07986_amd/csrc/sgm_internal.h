@@ -136,6 +136,6 @@ struct DetectGeom {
     double merge_iou;
 };
 hipError_t launch_detect(const DetectGeom &dg, const double *dhat, const double *dz, const uint8_t *flags,
-                         uint32_t *sat, uint8_t *fire, int32_t *boxes, int32_t *count, hipStream_t s);
+                         uint32_t *colp, uint32_t *sat, uint8_t *fire, int32_t *boxes, int32_t *count, hipStream_t s);
 
 }  // namespace sgmk

@@ -152,3 +152,27 @@ def test_static_scene_and_missing_predictions_give_nothing():
     dhat, dz, fl = _scene(W, H, [(50, 60, 120, 110)], 6.0)
     assert O.detect(dhat, dhat.copy(), fl)[0].shape == (0, 4)
     assert O.detect(dhat, dz, np.zeros_like(fl))[0].shape == (0, 4)
+
+
+def test_merging_every_overlap_ends_in_disjoint_bounding_boxes():
+    # with merge_iou = 0 the grouping stops only when no two boxes overlap;
+    # every input lies in exactly one result, and each result is the
+    # bounding box of the inputs inside it
+    rng = np.random.default_rng(11)
+    for _ in range(40):
+        n = int(rng.integers(1, 40))
+        xy = rng.integers(0, 150, (n, 2))
+        wh = rng.integers(1, 35, (n, 2))
+        boxes = np.concatenate([xy, xy + wh], axis=1).astype(np.int32)
+        out = O.merge_boxes(boxes)
+        for a in range(len(out)):
+            for b in range(a + 1, len(out)):
+                ia = min(out[a][2], out[b][2]) - max(out[a][0], out[b][0])
+                ib = min(out[a][3], out[b][3]) - max(out[a][1], out[b][1])
+                assert not (ia > 0 and ib > 0)
+        inside = [[k for k in range(n) if out[j][0] <= boxes[k][0] and out[j][1] <= boxes[k][1]
+                   and boxes[k][2] <= out[j][2] and boxes[k][3] <= out[j][3]] for j in range(len(out))]
+        assert sorted(k for ks in inside for k in ks) == list(range(n))
+        for j, ks in enumerate(inside):
+            sub = boxes[ks]
+            assert out[j].tolist() == [sub[:, 0].min(), sub[:, 1].min(), sub[:, 2].max(), sub[:, 3].max()]
