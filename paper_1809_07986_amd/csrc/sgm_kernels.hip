@@ -1484,7 +1484,13 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
     agg_args(g, b, hv, vv, nh, nv, maxv);
     if (!nh)
         return hipSuccess;
-    if (!dense) {
+    // Ragged windows: segmented scanlines (16 lanes per pixel, many waves)
+    // win for 64 < D <= 128; at D <= 64 one register chunk per lane and at
+    // D = 256 the wide windows favour one 64-lane wave per scanline.
+    bool segmented = !dense && g.D > 64 && g.D <= 128;
+    if (!dense && g.halt)
+        segmented = !segmented;
+    if (segmented) {
         const int seg = g.hseg;
         const int nseg = (g.W + seg - 1) / seg;
         const size_t lds2 = agg_h2_lds(g.D);

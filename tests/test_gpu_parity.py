@@ -268,6 +268,38 @@ def test_deterministic_repeat():
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name,W,H,D", [("tiny", 0, 0, 0), ("driving", 0, 0, 0), ("shape", 97, 41, 256),
+                                        ("shape", 83, 29, 100)])
+def test_both_horizontal_kernels_agree(name, W, H, D):
+    # reduced frames pick the horizontal kernel by max_disp; the debug bit
+    # selects the other one, which must give identical path losses and state
+    outs = []
+    for dbg in (0, NAT.DEBUG_ALT_HORIZONTAL):
+        _say(f"case: {name} {W}x{H}x{D}, debug {dbg}")
+        if name == "shape":
+            rng = np.random.default_rng(W + H + D)
+            left = rng.integers(0, 256, (H, W)).astype(np.uint8)
+            right = np.roll(left, -5, axis=1)
+            g = sgmk.ReducedSGM(W, H, D, f=100.0)
+            g.set_debug(dbg)
+            lo, hi = synth.random_windows(rng, H, W, D, max_width=40, full_frac=0.1)
+            g.match_windows(left, right, lo, hi)
+            torch.cuda.synchronize()
+            outs.append([_np(g.stage(NAT.STAGE_PATH0 + k)) for k in (0, 1)] +
+                        [_np(g.stage(NAT.STAGE_DSTAR)), _np(g.stage(NAT.STAGE_DZ))])
+            continue
+        seq = synth.make_sequence(name, frames=3)
+        g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, **_params(seq))
+        g.set_debug(dbg)
+        g.full_frame(seq.left[0], seq.right[0])
+        for k in (1, 2):
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+        torch.cuda.synchronize()
+        outs.append([_np(g.stage(NAT.STAGE_PATH0 + k)) for k in (0, 1)] + [_np(t) for t in g.get_state()])
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 def test_short_horizontal_segments_change_nothing():
     # 48-pixel segments: more segment starts, some whose restarted and exact
     # trajectories do not meet inside the segment (sequential fix-up pass)
