@@ -1124,9 +1124,8 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
             const bool act = chain_ok && x >= 0 && x < W;   // uniform per group
             const MetaEntry e = mb[r * AV_NG + grp];
             const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-            const bool wide = hi - lo >= AV_G;
-            const int c0 = wide ? (lo & ~(AV_G - 1)) : lo;
-            const int nt = !act ? 0 : (wide ? (hi >> 4) - (lo >> 4) + 1 : 1);
+            // chunks of 16 consecutive disparities from lo
+            const int nt = act ? ((hi - lo) >> 4) + 1 : 0;
             const int ntw = wave_max4(nt);
             if (ntw == 0)
                 continue;                                  // uniform over the wave
@@ -1134,19 +1133,21 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
             const int pb = ((cur ^ 1) * AV_NG + grp) * spad;
             const int cap = started ? mq + p2 : LBIG;      // the P2 term (none on the first pixel)
             const int sub = started ? mq : 0;
+            const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
             const uint64_t *crow = cb + (size_t)r * span;
-            const int cx0 = span_x0(t);
+            const int cbase = x - span_x0(t);
             int rmin = LBIG;
             for (int j = 0; j < ntw; j++) {
-                const int d = c0 + AV_G * j + lane;
-                const bool live = j < nt && d >= lo && d <= hi;
+                const int d = lo + AV_G * j + lane;
+                const bool live = j < nt && d <= hi;
                 const int dd = min(d, D);                  // keeps idle lanes inside the chain's slots
-                // unconditional reads; out-of-window terms become >= LBIG (absent)
+                // unconditional reads; out-of-window terms become LBIG (absent)
                 const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
-                const uint64_t crv = crow[max(x - dd - cx0, 0)];
-                const int a0 = max(v0, (dd >= loq && dd <= hiq) ? 0 : LBIG);
-                const int am = max(vm, (dd - 1 >= loq && dd - 1 <= hiq) ? 0 : LBIG);
-                const int ap = max(vp, (dd + 1 >= loq && dd + 1 <= hiq) ? 0 : LBIG);
+                const uint64_t crv = crow[max(cbase - dd, 0)];
+                const uint32_t tq = (uint32_t)(dd - loq);
+                const int a0 = tq <= spanq ? v0 : LBIG;
+                const int am = tq - 1u <= spanq ? vm : LBIG;
+                const int ap = tq + 1u <= spanq ? vp : LBIG;
                 const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
                 const int pc = __popcll(e.cl ^ crv);
                 const int c = dd > x ? nbits : pc;
@@ -1357,9 +1358,8 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const bool act = row_ok && !done;            // uniform per group (and per scanline in HS_FIX)
                 const MetaEntry e = mb[r * NC + cg];
                 const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-                const bool wide = hi - lo >= AV_G;
-                const int c0 = wide ? (lo & ~(AV_G - 1)) : lo;
-                const int nt = !act ? 0 : (wide ? (hi >> 4) - (lo >> 4) + 1 : 1);
+                // chunks of 16 consecutive disparities from lo
+                const int nt = act ? ((hi - lo) >> 4) + 1 : 0;
                 const int ntw = wave_max4(nt);
                 if (ntw == 0)
                     continue;                                  // uniform over the wave
@@ -1367,17 +1367,20 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const int pb = ((cur ^ 1) * AH2_NG + grp) * spad;
                 const int cap = started ? mq + p2 : LBIG;
                 const int sub = started ? mq : 0;
+                const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
+                const int cbase = x - cx0;
                 int rmin = LBIG;
                 bool diff = false;
                 for (int j = 0; j < ntw; j++) {
-                    const int d = c0 + AV_G * j + lane;
-                    const bool live = j < nt && d >= lo && d <= hi;
+                    const int d = lo + AV_G * j + lane;
+                    const bool live = j < nt && d <= hi;
                     const int dd = min(d, D);
                     const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
-                    const uint64_t crv = crow[max(x - dd - cx0, 0)];
-                    const int a0 = max(v0, (dd >= loq && dd <= hiq) ? 0 : LBIG);
-                    const int am = max(vm, (dd - 1 >= loq && dd - 1 <= hiq) ? 0 : LBIG);
-                    const int ap = max(vp, (dd + 1 >= loq && dd + 1 <= hiq) ? 0 : LBIG);
+                    const uint64_t crv = crow[max(cbase - dd, 0)];
+                    const uint32_t tq = (uint32_t)(dd - loq);
+                    const int a0 = tq <= spanq ? v0 : LBIG;
+                    const int am = tq - 1u <= spanq ? vm : LBIG;
+                    const int ap = tq + 1u <= spanq ? vp : LBIG;
                     const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
                     const int pc = __popcll(e.cl ^ crv);
                     const int c = dd > x ? nbits : pc;
