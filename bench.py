@@ -39,7 +39,8 @@ METRIC = "frames/s and cost-cells/s, reduced vs full SGM at 1242×375×128, 1 GP
 AGG_BYTES_PER_PIXEL_PATH = 22
 AGG_BYTES_PER_CELL_PATH = 1
 WTA_BYTES_PER_PIXEL = 53
-KERNEL_NAMES = {"agg_h": "k_agg_h (Eq. 1, horizontal paths)", "agg_v": "k_agg_v (Eq. 1, vertical + diagonal paths)",
+KERNEL_NAMES = {"agg_h": "k_agg_h2 speculative + fix-up + cleanup launches (Eq. 1, horizontal paths)",
+                "agg_v": "k_agg_v2 (Eq. 1, vertical + diagonal paths, ragged windows)",
                 "wta": "k_wta_correct (WTA, sub-pixel, Kalman, chi2)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_driving.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_07986_amd", "csrc", "sgm_kernels.hip")
