@@ -190,7 +190,8 @@ int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
 int sgm_set_debug(sgm_context *ctx, int32_t on);
 
 /* Per-stage GPU time, for benchmarks.  While profiling is on, every frame
- * records a HIP event before and after each stage's launches on the frame's
+ * (and every sgm_match_windows call, which counts as a frame) records a HIP
+ * event before and after each stage's launches on the frame's
  * own stream (events come from a pool made by sgm_set_profiling, so the
  * frame path still allocates nothing).  sgm_set_profiling(ctx, 1) starts a
  * new accumulation, 0 stops it.  sgm_read_profile synchronises `stream`,

@@ -32,7 +32,8 @@ struct sgm_context {
     bool debug;
     int device;
     Profiler prof;
-    hipStream_t side;           // horizontal aggregation runs here, forked from the caller's stream
+    hipStream_t side;           // census and horizontal aggregation run here, forked from the caller's stream
+    hipEvent_t fork0, cen;      // frame start on the caller's stream, census done on the side stream
     hipEvent_t fork, join;
     bool has_model;             // learned mode: sgm_set_window_model was called
 };
@@ -98,11 +99,11 @@ hipError_t dalloc(T **ptr, size_t count)
 
 void free_buffers(DevBuffers &b)
 {
-    void *all[] = {b.cen_l, b.cen_r, b.win,    b.off,    b.scan_part, b.cost,  b.lr,   b.sum,  b.d,   b.p,
-                   b.sflags, b.mask, b.dhat,   b.pm,     b.flags,     b.dstar, b.dz,   b.zkey, b.zidx, b.tgt,
-                   b.dprime, b.pprime, b.has, b.rw,     b.pred,      b.rst,   b.dw,   b.pw,   b.dfill, b.pfill,
-                   b.status, b.hflag, b.nu,   b.nu_w,   b.feat,   b.act_a,     b.act_b, b.cnn_out, b.hw, b.rpix, b.theta,
-                   b.frag};
+    void *all[] = {b.cen_l,  b.cen_r, b.win,    b.off,   b.scan_part, b.cost,  b.lr,    b.sum,     b.d,
+                   b.p,      b.sflags, b.mask,  b.dhat,  b.pm,        b.flags, b.dstar, b.dz,      b.zkey,
+                   b.zidx,   b.tgt,   b.dprime, b.pprime, b.has,      b.rw,    b.dw,    b.pw,      b.status,
+                   b.hflag,  b.nu,    b.nu_w,   b.feat,  b.act_a,     b.act_b, b.cnn_out, b.hw,    b.rpix,
+                   b.theta,  b.frag};
     for (void *p : all)
         if (p)
             (void)hipFree(p);
@@ -189,19 +190,35 @@ void prof_end_frame(Profiler &pf)
         pf.pending++;
 }
 
-// census, cost, aggregation, WTA (+ filter update in modes 0 and 1)
-int run_matcher(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, int mode, hipStream_t s,
-                bool marks = true)
+// Census of the frame's images on the side stream, concurrently with the
+// prediction (and the window network) on the caller's stream.
+int start_census(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t pitch, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(ctx->fork0, s);
+    if (e == hipSuccess)
+        e = hipStreamWaitEvent(ctx->side, ctx->fork0, 0);
+    if (e != hipSuccess)
+        return hip_fail(e, "stream fork");
+    StageMark mk(ctx->prof, ctx->side);
+    mk.begin(SGM_PROF_CENSUS);
+    e = launch_census(ctx->g, l, r, pitch, ctx->b.cen_l, ctx->b.cen_r, ctx->side);
+    mk.end(SGM_PROF_CENSUS);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->cen, ctx->side);
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "census launch");
+}
+
+// cost (debug), aggregation, WTA (+ filter update in modes 0 and 1) on the
+// census start_census launched for this frame
+int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true)
 {
     const Geometry &g = ctx->g;
     DevBuffers &b = ctx->b;
     // stages of a second matching pass are timed as a whole by the caller
     StageMark mk(marks ? ctx->prof : g_noprof, s);
-    mk.begin(SGM_PROF_CENSUS);
-    hipError_t e = launch_census(g, l, r, pitch, b.cen_l, b.cen_r, s);
-    mk.end(SGM_PROF_CENSUS);
+    hipError_t e = hipStreamWaitEvent(s, ctx->cen, 0);
     if (e != hipSuccess)
-        return hip_fail(e, "census launch");
+        return hip_fail(e, "census wait");
     if (ctx->debug) {
         // the matching cost is computed inside the aggregation; the stand-alone
         // cost kernel only materialises it for inspection
@@ -267,6 +284,9 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
     if (learned && !ctx->has_model)
         return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
     prof_begin_frame(ctx->prof, s);
+    int rc0 = start_census(ctx, left, right, pitch, s);
+    if (rc0)
+        return rc0;
     StageMark mk(ctx->prof, s);
     mk.begin(SGM_PROF_PREDICT);
     hipError_t e = launch_predict_core(ctx->g, ctx->b, wc, Tdev, correct_const(p), s);
@@ -290,7 +310,7 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
     e = launch_scan(ctx->g, ctx->b, s);
     if (e != hipSuccess)
         return hip_fail(e, "offset scan launch");
-    int rc = run_matcher(ctx, left, right, pitch, 1, s);
+    int rc = run_matcher(ctx, 1, s);
     if (rc)
         return rc;
     if (p.gate_rerun) {
@@ -302,7 +322,7 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
             e = launch_scan(ctx->g, ctx->b, s);
         if (e != hipSuccess)
             return hip_fail(e, "gate re-run launch");
-        rc = run_matcher(ctx, left, right, pitch, 1, s, false);
+        rc = run_matcher(ctx, 1, s, false);
         mk.end(SGM_PROF_RERUN);
         if (rc)
             return rc;
@@ -316,10 +336,13 @@ int full_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *right,
     if (ctx->prm.window_mode == SGM_WIN_LEARNED && !ctx->has_model)
         return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
     prof_begin_frame(ctx->prof, s);
+    int rc = start_census(ctx, left, right, pitch, s);
+    if (rc)
+        return rc;
     hipError_t e = launch_full_windows(ctx->g, ctx->b, s);
     if (e != hipSuccess)
         return hip_fail(e, "window launch");
-    int rc = run_matcher(ctx, left, right, pitch, 0, s);
+    rc = run_matcher(ctx, 0, s);
     if (rc)
         return rc;
     prof_end_frame(ctx->prof);
@@ -438,12 +461,8 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.pprime, N));
     A(dalloc(&b.has, N));
     A(dalloc(&b.rw, N));
-    A(dalloc(&b.pred, N));
-    A(dalloc(&b.rst, N));
     A(dalloc(&b.dw, N));
     A(dalloc(&b.pw, N));
-    A(dalloc(&b.dfill, N));
-    A(dalloc(&b.pfill, N));
     A(dalloc(&b.status, 4));
     A(dalloc(&b.hflag, (size_t)2 * g.H * kHMaxSeg));
     A(dalloc(&b.nu, N));
@@ -486,10 +505,19 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     }
     e = hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking);
     if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->fork0, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipEventCreateWithFlags(&ctx->cen, hipEventDisableTiming);
+    if (e == hipSuccess)
         e = hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming);
     if (e == hipSuccess)
         e = hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming);
     if (e != hipSuccess) {
+        for (hipEvent_t ev : {ctx->fork0, ctx->cen, ctx->fork, ctx->join})
+            if (ev)
+                (void)hipEventDestroy(ev);
+        if (ctx->side)
+            (void)hipStreamDestroy(ctx->side);
         free_buffers(b);
         delete ctx;
         return hip_fail(e, "stream/event creation");
@@ -506,6 +534,8 @@ void sgm_destroy(sgm_context *ctx)
     if (!ctx)
         return;
     (void)hipDeviceSynchronize();
+    (void)hipEventDestroy(ctx->fork0);
+    (void)hipEventDestroy(ctx->cen);
     (void)hipEventDestroy(ctx->fork);
     (void)hipEventDestroy(ctx->join);
     (void)hipStreamDestroy(ctx->side);
@@ -608,12 +638,17 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
     if (!lo || !hi || !dstar || !dz)
         return fail(SGM_EINVAL, "window or output pointer is NULL");
     hipStream_t s = as_stream(stream);
+    prof_begin_frame(ctx->prof, s);
+    rc = start_census(ctx, left, right, pitch, s);
+    if (rc)
+        return rc;
     hipError_t e = launch_given_windows(ctx->g, ctx->b, lo, hi, s);
     if (e != hipSuccess)
         return hip_fail(e, "window launch");
-    rc = run_matcher(ctx, left, right, pitch, 2, s);
+    rc = run_matcher(ctx, 2, s);
     if (rc)
         return rc;
+    prof_end_frame(ctx->prof);
     const size_t N = ctx->g.N;
     e = hipMemcpyAsync(dstar, ctx->b.dstar, N * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
     if (e == hipSuccess)

@@ -38,8 +38,8 @@ struct DevBuffers {
     uint32_t *zidx;            // min source index among the max-d' sources
     int32_t *tgt;              // target per source (-1 dropped)
     double *dprime, *pprime;   // splatted disparity / variance per source
-    uint8_t *has, *rw, *pred, *rst;
-    double *dw, *pw, *dfill, *pfill;
+    uint8_t *has, *rw;
+    double *dw, *pw;
     uint32_t *status;
     uint8_t *hflag;            // horizontal aggregation: flagged segments [2][H][kHMaxSeg]
     // learned window (allocated in learned mode only, except nu / nu_w)

@@ -23,7 +23,9 @@ namespace sgmk {
 template <int N>
 __device__ __forceinline__ int row_ror(int v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, 0x120 + N, 0xF, 0xF, false);
+    // every lane has a source, so the "old" operand is never used and the
+    // move can fold into the instruction that consumes it
+    return __builtin_amdgcn_mov_dpp(v, 0x120 + N, 0xF, 0xF, true);
 }
 
 // min over the 16 lanes of a DPP row; every lane receives the result
@@ -301,82 +303,97 @@ __global__ void k_splat_resolve(int N, unsigned long long *__restrict__ zkey, ui
 // zooming holes: a target without a winner whose left & right (or upper &
 // lower) neighbours both have winners takes their mean disparity and mean
 // variance; with both pairs, the mean of four (summed left, right, up, down)
-__global__ void k_fill(int W, int H, const uint8_t *__restrict__ has, const double *__restrict__ dw,
-                       const double *__restrict__ pw, const uint8_t *__restrict__ rw, uint8_t *__restrict__ pred,
-                       double *__restrict__ dfill, double *__restrict__ pfill, uint8_t *__restrict__ rst)
+__device__ __forceinline__ void fill_hole(int W, int H, int t, int x, int y, const uint8_t *__restrict__ has,
+                                          const double *__restrict__ dw, const double *__restrict__ pw,
+                                          const uint8_t *__restrict__ rw, uint8_t &pr, double &dv, double &pv,
+                                          uint8_t &rv)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= W * H)
+    pr = has[t];
+    dv = dw[t];
+    pv = pw[t];
+    rv = rw[t];
+    if (pr)
         return;
-    int y = t / W, x = t - y * W;
-    uint8_t pr = has[t];
-    double dv = dw[t], pv = pw[t];
-    uint8_t rv = rw[t];
-    if (!pr) {
-        bool hp = x - 1 >= 0 && x + 1 < W && has[t - 1] && has[t + 1];
-        bool vp = y - 1 >= 0 && y + 1 < H && has[t - W] && has[t + W];
-        if (hp && vp) {
-            dv = (((dw[t - 1] + dw[t + 1]) + dw[t - W]) + dw[t + W]) / 4.0;
-            pv = (((pw[t - 1] + pw[t + 1]) + pw[t - W]) + pw[t + W]) / 4.0;
-            rv = rw[t - 1] | rw[t + 1] | rw[t - W] | rw[t + W];
-            pr = 1;
-        } else if (hp) {
-            dv = (dw[t - 1] + dw[t + 1]) / 2.0;
-            pv = (pw[t - 1] + pw[t + 1]) / 2.0;
-            rv = rw[t - 1] | rw[t + 1];
-            pr = 1;
-        } else if (vp) {
-            dv = (dw[t - W] + dw[t + W]) / 2.0;
-            pv = (pw[t - W] + pw[t + W]) / 2.0;
-            rv = rw[t - W] | rw[t + W];
-            pr = 1;
-        }
+    const bool hp = x - 1 >= 0 && x + 1 < W && has[t - 1] && has[t + 1];
+    const bool vp = y - 1 >= 0 && y + 1 < H && has[t - W] && has[t + W];
+    if (hp && vp) {
+        dv = (((dw[t - 1] + dw[t + 1]) + dw[t - W]) + dw[t + W]) / 4.0;
+        pv = (((pw[t - 1] + pw[t + 1]) + pw[t - W]) + pw[t + W]) / 4.0;
+        rv = rw[t - 1] | rw[t + 1] | rw[t - W] | rw[t + W];
+        pr = 1;
+    } else if (hp) {
+        dv = (dw[t - 1] + dw[t + 1]) / 2.0;
+        pv = (pw[t - 1] + pw[t + 1]) / 2.0;
+        rv = rw[t - 1] | rw[t + 1];
+        pr = 1;
+    } else if (vp) {
+        dv = (dw[t - W] + dw[t + W]) / 2.0;
+        pv = (pw[t - W] + pw[t + W]) / 2.0;
+        rv = rw[t - W] | rw[t + W];
+        pr = 1;
     }
-    pred[t] = pr;
-    dfill[t] = dv;
-    pfill[t] = pv;
-    rst[t] = rv;
 }
 
-// discontinuity rejection (8-neighbourhood of the filled map, decided before
-// any rejection) and the search limits d^ +- k sigma, rounded outward
-__global__ void k_disc_windows(int W, int H, int D, CorrectConst cc, const uint8_t *__restrict__ pred,
-                               const double *__restrict__ dfill, const double *__restrict__ pfill,
-                               const uint8_t *__restrict__ rst, uint8_t *__restrict__ flags,
-                               uint16_t *__restrict__ win, double *__restrict__ dhat, double *__restrict__ pm,
-                               double *__restrict__ nu_w)
+// Hole fill, then discontinuity rejection (8-neighbourhood of the filled
+// map, decided before any rejection) and the search limits d^ +- k sigma,
+// rounded outward.  A block fills a 64 x 4 tile plus a one-pixel halo in
+// LDS, so the filled map never goes to memory.
+constexpr int FD_TW = 64, FD_TH = 4, FD_LW = FD_TW + 2, FD_LN = FD_LW * (FD_TH + 2);
+
+__global__ __launch_bounds__(FD_TW *FD_TH) void k_fill_disc(int W, int H, int D, CorrectConst cc,
+                                                            const uint8_t *__restrict__ has,
+                                                            const double *__restrict__ dw,
+                                                            const double *__restrict__ pw,
+                                                            const uint8_t *__restrict__ rw, uint8_t *__restrict__ flags,
+                                                            uint16_t *__restrict__ win, double *__restrict__ dhat,
+                                                            double *__restrict__ pm, double *__restrict__ nu_w)
 {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= W * H)
+    __shared__ double sd[FD_LN], sp[FD_LN];
+    __shared__ uint8_t spr[FD_LN], srs[FD_LN];
+    const int x0 = blockIdx.x * FD_TW - 1, y0 = blockIdx.y * FD_TH - 1;
+    for (int i = threadIdx.x; i < FD_LN; i += FD_TW * FD_TH) {
+        const int ly = i / FD_LW, lx = i - ly * FD_LW;
+        const int x = x0 + lx, y = y0 + ly;
+        uint8_t pr = 0, rv = 0;
+        double dv = 0.0, pv = 0.0;
+        if (x >= 0 && x < W && y >= 0 && y < H)
+            fill_hole(W, H, y * W + x, x, y, has, dw, pw, rw, pr, dv, pv, rv);
+        spr[i] = pr;   // outside the image: no prediction (no neighbour)
+        sd[i] = dv;
+        sp[i] = pv;
+        srs[i] = rv;
+    }
+    __syncthreads();
+    const int lx = threadIdx.x % FD_TW + 1, ly = threadIdx.x / FD_TW + 1;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= W || y >= H)
         return;
-    int y = t / W, x = t - y * W;
-    bool ok = pred[t];
-    double dv = dfill[t];
+    const int c = ly * FD_LW + lx, t = y * W + x;
+    bool ok = spr[c];
+    const double dv = sd[c];
     if (ok) {
-        for (int yy = y - 1; yy <= y + 1; yy++) {
-            for (int xx = x - 1; xx <= x + 1; xx++) {
-                if (xx < 0 || xx >= W || yy < 0 || yy >= H || (xx == x && yy == y))
-                    continue;
-                int u = yy * W + xx;
-                if (pred[u] && fabs(dv - dfill[u]) > cc.disc)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                const int u = c + dy * FD_LW + dx;
+                if ((dx || dy) && spr[u] && fabs(dv - sd[u]) > cc.disc)
                     ok = false;
             }
-        }
     }
+    const uint8_t rs = srs[c];
     uint8_t fl = 0;
     if (ok)
         fl |= SGM_FLAG_PRED;
-    if (rst[t])
+    if (rs)
         fl |= SGM_FLAG_RESET;
-    bool full = !ok || rst[t] || !(dv >= 0.0 && dv <= (double)(D - 1));
-    double pv = pfill[t];
+    const bool full = !ok || rs || !(dv >= 0.0 && dv <= (double)(D - 1));
+    const double pv = sp[c];
     if (full) {
         fl |= SGM_FLAG_FULLWIN;
         win[t] = pack_win(0, D - 1);
     } else {
-        double sd = sqrt(pv);
-        double a = dv - cc.k_sigma * sd;
-        double b = dv + cc.k_sigma * sd;
+        const double sdv = sqrt(pv);
+        const double a = dv - cc.k_sigma * sdv;
+        const double b = dv + cc.k_sigma * sdv;
         int l = (int)floor(a), h = (int)ceil(b);
         l = l < 0 ? 0 : l;
         h = h > D - 1 ? D - 1 : h;
@@ -407,16 +424,15 @@ hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst
     hipLaunchKernelGGL(k_splat_ties, grd, blk, 0, s, g.N, b.tgt, b.dprime, b.zkey, b.zidx);
     hipLaunchKernelGGL(k_splat_resolve, grd, blk, 0, s, g.N, b.zkey, b.zidx, b.dprime, b.pprime, b.sflags, b.nu,
                        b.has, b.dw, b.pw, b.rw, b.nu_w);
-    hipLaunchKernelGGL(k_fill, grd, blk, 0, s, g.W, g.H, b.has, b.dw, b.pw, b.rw, b.pred, b.dfill, b.pfill, b.rst);
-    hipLaunchKernelGGL(k_disc_windows, grd, blk, 0, s, g.W, g.H, g.D, cc, b.pred, b.dfill, b.pfill, b.rst, b.flags,
-                       b.win, b.dhat, b.pm, b.nu_w);
+    hipLaunchKernelGGL(k_fill_disc, dim3((g.W + FD_TW - 1) / FD_TW, (g.H + FD_TH - 1) / FD_TH), dim3(FD_TW * FD_TH), 0,
+                       s, g.W, g.H, g.D, cc, b.has, b.dw, b.pw, b.rw, b.flags, b.win, b.dhat, b.pm, b.nu_w);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// ragged offsets: exclusive prefix sum of the window widths.
-// Three phases: per-block scan (4096 pixels per block), scan of the block
-// totals in one block, add-back.  off[N] is the total cell count M.
+// ragged offsets: exclusive prefix sum of the window widths (4096 pixels
+// per block, see k_scan_sums / k_scan_apply).  off[N] is the total cell
+// count M.
 // ---------------------------------------------------------------------------
 
 constexpr int SCAN_T = 1024, SCAN_PER = 4, SCAN_BLOCK = SCAN_T * SCAN_PER;
@@ -453,68 +469,62 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
     return incl - v + wsum[wv];
 }
 
-__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(int N, const uint16_t *__restrict__ win,
-                                                        uint32_t *__restrict__ off, uint32_t *__restrict__ part)
+// Two passes: the window widths summed per block of SCAN_BLOCK pixels, then
+// each block adds the sums of the blocks before it to its own exclusive scan
+// (the block sums are few, so every block reads them all).
+__global__ __launch_bounds__(SCAN_T) void k_scan_sums(int N, const uint16_t *__restrict__ win,
+                                                      uint32_t *__restrict__ part)
 {
     __shared__ uint32_t tot;
+    const int base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER;
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < SCAN_PER; i++) {
+        const int p = base + i;
+        sum += p < N ? (uint32_t)(win[p] >> 8) + 1u : 0u;
+    }
+    (void)block_excl_scan(sum, &tot);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_apply(int N, const uint16_t *__restrict__ win,
+                                                       uint32_t *__restrict__ off,
+                                                       const uint32_t *__restrict__ part)
+{
+    __shared__ uint32_t tot, before_tot;
+    // sum of the block sums before this block
+    uint32_t pre = 0;
+    for (int i = threadIdx.x; i < (int)blockIdx.x; i += SCAN_T)
+        pre += part[i];
+    (void)block_excl_scan(pre, &before_tot);
+    const uint32_t before = before_tot;
     const int base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER;
     uint32_t w[SCAN_PER];
     uint32_t sum = 0;
 #pragma unroll
     for (int i = 0; i < SCAN_PER; i++) {
-        int p = base + i;
+        const int p = base + i;
         w[i] = p < N ? (uint32_t)(win[p] >> 8) + 1u : 0u;
         sum += w[i];
     }
-    uint32_t ex = block_excl_scan(sum, &tot);
+    uint32_t ex = before + block_excl_scan(sum, &tot);
 #pragma unroll
     for (int i = 0; i < SCAN_PER; i++) {
-        int p = base + i;
+        const int p = base + i;
         if (p < N)
             off[p] = ex;
         ex += w[i];
     }
-    if (threadIdx.x == 0)
-        part[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(SCAN_T) void k_scan_parts(int nparts, uint32_t *__restrict__ part)
-{
-    __shared__ uint32_t tot;
-    const int base = threadIdx.x * SCAN_PER;
-    uint32_t w[SCAN_PER];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int i = 0; i < SCAN_PER; i++) {
-        w[i] = base + i < nparts ? part[base + i] : 0u;
-        sum += w[i];
-    }
-    uint32_t ex = block_excl_scan(sum, &tot);
-#pragma unroll
-    for (int i = 0; i < SCAN_PER; i++) {
-        if (base + i < nparts)
-            part[base + i] = ex;
-        ex += w[i];
-    }
-    if (threadIdx.x == 0)
-        part[nparts] = tot;
-}
-
-__global__ void k_scan_add(int N, int nparts, uint32_t *__restrict__ off, const uint32_t *__restrict__ part)
-{
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < N)
-        off[p] += part[p / SCAN_BLOCK];
-    else if (p == N)
-        off[N] = part[nparts];
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0)
+        off[N] = before + tot;
 }
 
 hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s)
 {
     int nparts = (g.N + SCAN_BLOCK - 1) / SCAN_BLOCK;   // <= SCAN_BLOCK, checked at create
-    hipLaunchKernelGGL(k_scan_blocks, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.off, b.scan_part);
-    hipLaunchKernelGGL(k_scan_parts, dim3(1), dim3(SCAN_T), 0, s, nparts, b.scan_part);
-    hipLaunchKernelGGL(k_scan_add, dim3((g.N + 1 + 255) / 256), dim3(256), 0, s, g.N, nparts, b.off, b.scan_part);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.scan_part);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.off, b.scan_part);
     return hipGetLastError();
 }
 
@@ -1553,14 +1563,24 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
 // ---------------------------------------------------------------------------
 // winner-takes-all (Section 2.3) with parabolic sub-pixel fit, then the
 // Kalman correction (Eq. 5-6) and the innovation test (Section 4).
-// A group of 16 lanes (a DPP row) handles one pixel: lanes sum the paths'
-// L_r over the window (S), keep S in LDS and reduce (S << 9 | slot), which
-// picks the smallest S and then the lowest disparity.  Lane 0 then fits the
-// parabola through S(d*-1), S(d*), S(d*+1) and updates the filter in double
-// precision.
+// A group of 8 lanes (half a DPP row) handles one pixel: lanes sum the
+// paths' L_r over the window (S), keep S in LDS and reduce (S << 9 | slot),
+// which picks the smallest S and then the lowest disparity.  Lane 0 then
+// fits the parabola through S(d*-1), S(d*), S(d*+1) and updates the filter
+// in double precision.  Eight lanes cover a window of up to 29 cells in one
+// pass (typical reduced windows have 8-10).
 // ---------------------------------------------------------------------------
 
-constexpr int WTA_G = 16, WTA_NG = 16, WTA_T = WTA_G * WTA_NG;
+constexpr int WTA_G = 8, WTA_NG = 32, WTA_T = WTA_G * WTA_NG;
+
+// min over the 8 lanes of a half DPP row; every lane receives the result
+__device__ __forceinline__ int half_row_min8(int v)
+{
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));   // row_half_mirror
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));    // quad_perm [2,3,0,1]
+    v = min(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));    // quad_perm [1,0,3,2]
+    return v;
+}
 
 __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths, CorrectConst cc, int mode,
                                                        const uint8_t *__restrict__ lr, size_t lr_stride,
@@ -1610,7 +1630,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
             }
         }
     }
-    key = (uint32_t)row_min16((int)key);   // keys < 2^31: the signed min is the unsigned min
+    key = (uint32_t)half_row_min8((int)key);   // keys < 2^31: the signed min is the unsigned min
     wave_lds_sync();
     if (lane != 0)
         return;
