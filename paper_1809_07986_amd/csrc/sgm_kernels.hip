@@ -659,6 +659,8 @@ template <int G>
 __device__ __forceinline__ int group_min(int v)
 {
     v = row_min16(v);
+    if (G == 32)
+        v = min(v, __shfl_xor(v, 16, 64));
     if (G == 64) {
         int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
         int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
@@ -1031,7 +1033,15 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
 // the 16-aligned chunks it touches.  The chunk loop runs to the largest count
 // of the wave's four chains, so a narrow step costs one chunk.
 
-constexpr int AV2_PAD = 18;   // state slots past D: chunk lanes reach lo+15, plus d+1
+// max of a group-uniform value over the groups of G lanes of a wave
+template <int G>
+__device__ __forceinline__ int group_max(int v)
+{
+    if (G == 16)
+        return wave_max4(v);
+    return max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
+}
+constexpr int AV2_PAD = 18;   // state slots past D (idle lanes are clamped to D), plus d+1
 
 __host__ __device__ constexpr int agg_v2_spad(int D) { return (D + AV2_PAD + 1) & ~1; }
 
@@ -1042,10 +1052,10 @@ __host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
 }
 
 // NG chains per block (NG / 4 waves), B rows per staged batch
-template <int NG, int B>
-__global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
+template <int NG, int B, int G>
+__device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
 {
-    constexpr int AV_NG = NG, AV_B = B, AV_T = NG * AV_G;
+    constexpr int AV_NG = NG, AV_B = B, AV_T = NG * G;
     constexpr int AV_MAXCR = (AV_B * (AV_NG + kMaxDisp - 1) + AV_T - 1) / AV_T;   // per thread
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
@@ -1055,7 +1065,6 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
     MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AV_B * span * 8);          // [2][B][NG]
     uint16_t *sbuf = (uint16_t *)(smem + (size_t)2 * AV_B * span * 8 +
                                   (size_t)2 * AV_B * AV_NG * sizeof(MetaEntry));  // [2][NG][spad]
-    const int pi = blockIdx.y;
     const int k = a.slot[pi];
     const int rx = a.rx[pi], ry = a.ry[pi];
     const int kmin = a.kmin[pi];
@@ -1063,7 +1072,7 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
     if (blockIdx.x * AV_NG >= nchains)
         return;                                        // uniform over the block
     const int kb = kmin + blockIdx.x * AV_NG;          // chain index of group 0
-    const int grp = threadIdx.x / AV_G, lane = threadIdx.x % AV_G;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int kc = kb + grp;
     const bool chain_ok = blockIdx.x * AV_NG + grp < nchains;
     const int ys = ry > 0 ? 0 : H - 1;
@@ -1134,9 +1143,9 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
             const bool act = chain_ok && x >= 0 && x < W;   // uniform per group
             const MetaEntry e = mb[r * AV_NG + grp];
             const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-            // chunks of 16 consecutive disparities from lo
-            const int nt = act ? ((hi - lo) >> 4) + 1 : 0;
-            const int ntw = wave_max4(nt);
+            // chunks of G consecutive disparities from lo
+            const int nt = act ? (hi - lo) / G + 1 : 0;
+            const int ntw = group_max<G>(nt);
             if (ntw == 0)
                 continue;                                  // uniform over the wave
             const int qb = (cur * AV_NG + grp) * spad;     // previous pixel's L_r (slot d + 1)
@@ -1148,7 +1157,7 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
             const int cbase = x - span_x0(t);
             int rmin = LBIG;
             for (int j = 0; j < ntw; j++) {
-                const int d = lo + AV_G * j + lane;
+                const int d = lo + G * j + lane;
                 const bool live = j < nt && d <= hi;
                 const int dd = min(d, D);                  // keeps idle lanes inside the chain's slots
                 // unconditional reads; out-of-window terms become LBIG (absent)
@@ -1168,7 +1177,7 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
                 }
                 rmin = min(rmin, L);
             }
-            const int m = row_min16(rmin);
+            const int m = group_min<G>(rmin);
             if (act) {
                 mq = m;
                 loq = lo;
@@ -1181,6 +1190,19 @@ __global__ __launch_bounds__(NG * 16) void k_agg_v2(AggArgs a)
         commit((bt + 1) & 1);
         __syncthreads();
     }
+}
+
+// Vertical chains get 32 lanes each (8 per block): full-range pixels line up
+// along some columns (the left border, vertical edges) and would otherwise
+// make a few blocks take twice as long as the rest; diagonal chains cross
+// such columns and keep 16 lanes (16 per block).
+__global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
+{
+    const int pi = blockIdx.y;
+    if (a.rx[pi] == 0)
+        agg_v2_chains<8, 8, 32>(a, pi);
+    else
+        agg_v2_chains<16, 8, 16>(a, pi);
 }
 
 // ---- horizontal paths: 16 scanlines per block, LDS state, segments --------
@@ -1555,8 +1577,10 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
         return hipGetLastError();
     }
     // ragged windows: LDS-resident state, chunk count per pixel
-    dim3 grd((maxv + AV_NG - 1) / AV_NG, nv);
-    hipLaunchKernelGGL((k_agg_v2<16, 8>), grd, dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
+    int nbx = 0;
+    for (int i = 0; i < nv; i++)
+        nbx = max(nbx, vv.rx[i] == 0 ? (g.W + 7) / 8 : (g.W + g.H - 1 + 15) / 16);
+    hipLaunchKernelGGL(k_agg_v2, dim3(nbx, nv), dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
     return hipGetLastError();
 }
 
