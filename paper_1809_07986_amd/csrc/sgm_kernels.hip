@@ -1587,15 +1587,15 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
 // ---------------------------------------------------------------------------
 // winner-takes-all (Section 2.3) with parabolic sub-pixel fit, then the
 // Kalman correction (Eq. 5-6) and the innovation test (Section 4).
-// A group of 8 lanes (half a DPP row) handles one pixel: lanes sum the
-// paths' L_r over the window (S), keep S in LDS and reduce (S << 9 | slot),
-// which picks the smallest S and then the lowest disparity.  Lane 0 then
-// fits the parabola through S(d*-1), S(d*), S(d*+1) and updates the filter
-// in double precision.  Eight lanes cover a window of up to 29 cells in one
-// pass (typical reduced windows have 8-10).
+// A group of WG lanes handles one pixel: lanes sum the paths' L_r over the
+// window (S), keep S in LDS and reduce (S << 9 | slot), which picks the
+// smallest S and then the lowest disparity.  Lane 0 then fits the parabola
+// through S(d*-1), S(d*), S(d*+1) and updates the filter in double
+// precision.  Reduced frames use 8 lanes (half a DPP row; up to 29 cells in
+// one pass, typical reduced windows have 8-10), full-range frames 16.
 // ---------------------------------------------------------------------------
 
-constexpr int WTA_G = 8, WTA_NG = 32, WTA_T = WTA_G * WTA_NG;
+constexpr int WTA_T = 256;
 
 // min over the 8 lanes of a half DPP row; every lane receives the result
 __device__ __forceinline__ int half_row_min8(int v)
@@ -1606,6 +1606,7 @@ __device__ __forceinline__ int half_row_min8(int v)
     return v;
 }
 
+template <int WG>
 __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths, CorrectConst cc, int mode,
                                                        const uint8_t *__restrict__ lr, size_t lr_stride,
                                                        const uint16_t *__restrict__ win,
@@ -1618,9 +1619,10 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags,
                                                        const float *__restrict__ rpix, double *__restrict__ nu_out)
 {
-    __shared__ uint16_t ssum[WTA_NG][kMaxDisp + 8];
-    const int grp = threadIdx.x / WTA_G, lane = threadIdx.x % WTA_G;
-    const int t = blockIdx.x * WTA_NG + grp;
+    constexpr int WNG = WTA_T / WG;   // pixels per block
+    __shared__ uint16_t ssum[WNG][kMaxDisp + 8];
+    const int grp = threadIdx.x / WG, lane = threadIdx.x % WG;
+    const int t = blockIdx.x * WNG + grp;
     if (t >= N)
         return;   // the whole group leaves together
     const uint32_t o = off[t];
@@ -1634,7 +1636,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     const int lead = (int)(o - a0);           // cells of the previous pixel in it
     const int ndw = (lead + w + 3) >> 2;
     uint32_t key = 0x7FFFFFFFu;   // above every real key (S << 9 | slot < 2^20)
-    for (int q = lane; q < ndw; q += WTA_G) {
+    for (int q = lane; q < ndw; q += WG) {
         const uint32_t byte0 = a0 + 4u * (uint32_t)q;
         uint32_t ev = 0, od = 0;
         for (int k = 0; k < npaths; k++) {
@@ -1654,7 +1656,8 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
             }
         }
     }
-    key = (uint32_t)half_row_min8((int)key);   // keys < 2^31: the signed min is the unsigned min
+    // keys < 2^31: the signed min is the unsigned min
+    key = (uint32_t)(WG == 8 ? half_row_min8((int)key) : row_min16((int)key));
     wave_lds_sync();
     if (lane != 0)
         return;
@@ -1707,7 +1710,13 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
                               bool debug_sum, const float *rpix, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_wta_correct, dim3((g.N + WTA_NG - 1) / WTA_NG), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
+    if (mode == 0)
+        hipLaunchKernelGGL((k_wta_correct<16>), dim3((g.N + 15) / 16), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
+                       mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
+                       debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
+                       b.nu);
+    else
+        hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
                        b.nu);
