@@ -1025,13 +1025,13 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
 
 // ---- vertical and diagonal paths, LDS-resident recurrence state ----------
 //
-// Same staging as k_agg_v (16 chains per block, 8-row batches of right census
-// and pixel metadata in LDS), but each chain keeps the previous pixel's L_r in
-// LDS, indexed by absolute disparity, and reads its d-1, d, d+1 terms back
-// masked by that pixel's window.  A pixel with a window of at most 16 cells is
-// one 16-lane chunk starting at its lower bound; a wider window is covered by
-// the 16-aligned chunks it touches.  The chunk loop runs to the largest count
-// of the wave's four chains, so a narrow step costs one chunk.
+// Staging as in k_agg_v (NG chains per block, 8-row batches of right census
+// and pixel metadata in LDS), but each chain (a group of G lanes) keeps the
+// previous pixel's L_r in LDS, indexed by absolute disparity, and reads its
+// d-1, d, d+1 terms back masked by that pixel's window.  A step covers the
+// window in chunks of G consecutive disparities from its lower bound; the
+// chunk loop runs to the largest count among the wave's chains, so a narrow
+// step costs one chunk.
 
 // max of a group-uniform value over the groups of G lanes of a wave
 template <int G>
@@ -1205,7 +1205,7 @@ __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
         agg_v2_chains<16, 8, 16>(a, pi);
 }
 
-// ---- horizontal paths: 16 scanlines per block, LDS state, segments --------
+// ---- horizontal paths: 256 / G scanlines per block, LDS state, segments ----
 //
 // Scanline y of a horizontal direction is cut into segments of `seg` steps
 // (step t is column rx > 0 ? t : W-1-t).  Three kernels:
@@ -1240,21 +1240,22 @@ __host__ __device__ constexpr size_t agg_h2_lds(int D)
            (size_t)2 * AH2_NG * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
-template <int MODE>
+template <int MODE, int G>
 __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
 {
-    constexpr int NC = MODE == HS_FIX ? AH2_NG / 2 : AH2_NG;   // scanlines per block
+    constexpr int NGG = AH2_T / G;                          // groups of G lanes per block
+    constexpr int NC = MODE == HS_FIX ? NGG / 2 : NGG;       // scanlines per block
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
     const int span = agg_h2_span(D), spad = agg_v2_spad(D);
     uint64_t *cbuf = (uint64_t *)smem;                                               // [2][NC][span]
-    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AH2_NG * span * 8);           // [2][B][NC]
-    uint16_t *sbuf = (uint16_t *)((uint8_t *)mbuf + (size_t)2 * AH2_B * AH2_NG * sizeof(MetaEntry));
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * NGG * span * 8);              // [2][B][NC]
+    uint16_t *sbuf = (uint16_t *)((uint8_t *)mbuf + (size_t)2 * AH2_B * NGG * sizeof(MetaEntry));
     const int pi = blockIdx.z;
     const int k = a.slot[pi];
     const int rx = a.rx[pi];
     const int y0 = blockIdx.x * NC;
-    const int grp = threadIdx.x / AV_G, lane = threadIdx.x % AV_G;
+    const int grp = threadIdx.x / G, lane = threadIdx.x % G;
     const int cg = MODE == HS_FIX ? grp >> 1 : grp;   // scanline of this group
     const bool traj_a = MODE != HS_FIX || (grp & 1) == 0;
     const int y = y0 + cg;
@@ -1307,7 +1308,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
         }
     };
     auto commit = [&](int buf) {
-        uint64_t *cb = cbuf + (size_t)buf * AH2_NG * span;
+        uint64_t *cb = cbuf + (size_t)buf * NGG * span;
 #pragma unroll
         for (int i = 0; i < AH2_MAXCR; i++) {
             const int e = threadIdx.x + i * AH2_T;
@@ -1319,7 +1320,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             m.cl = rmcl;
             m.off = rmoff;
             m.win = rmwin;
-            mbuf[buf * AH2_B * AH2_NG + threadIdx.x] = m;
+            mbuf[buf * AH2_B * NGG + threadIdx.x] = m;
         }
     };
 
@@ -1349,19 +1350,19 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             const uint32_t wv = a.win[p];
             const uint32_t off = a.off[p];
             const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
-            const int nt = load ? (hi >> 4) - (lo >> 4) + 1 : 0;
-            const int ntw = wave_max4(nt);
-            const int qb = (cur * AH2_NG + grp) * spad;
+            const int nt = load ? hi / G - lo / G + 1 : 0;
+            const int ntw = group_max<G>(nt);
+            const int qb = (cur * NGG + grp) * spad;
             int rmin = LBIG;
             for (int j = 0; j < ntw; j++) {
-                const int d = (lo & ~(AV_G - 1)) + AV_G * j + lane;
+                const int d = (lo / G) * G + G * j + lane;
                 if (j < nt && d >= lo && d <= hi) {
                     const int v = lrk[off + (uint32_t)(d - lo)];
                     sbuf[qb + d + 1] = (uint16_t)v;
                     rmin = min(rmin, v);
                 }
             }
-            const int m = row_min16(rmin);
+            const int m = group_min<G>(rmin);
             if (load) {
                 mq = m;
                 loq = lo;
@@ -1381,8 +1382,8 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             const int tb = t0 + bt * AH2_B;
             if (bt + 1 < nbt)
                 issue(tb + AH2_B, t1);
-            const uint64_t *crow = cbuf + (size_t)(bt & 1) * AH2_NG * span + (size_t)cg * span;
-            const MetaEntry *mb = mbuf + (bt & 1) * AH2_B * AH2_NG;
+            const uint64_t *crow = cbuf + (size_t)(bt & 1) * NGG * span + (size_t)cg * span;
+            const MetaEntry *mb = mbuf + (bt & 1) * AH2_B * NGG;
             const int cx0 = span_x0(tb);
             const int rows = min(AH2_B, t1 - tb);
             for (int r = 0; r < rows; r++) {
@@ -1390,13 +1391,13 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const bool act = row_ok && !done;            // uniform per group (and per scanline in HS_FIX)
                 const MetaEntry e = mb[r * NC + cg];
                 const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-                // chunks of 16 consecutive disparities from lo
-                const int nt = act ? ((hi - lo) >> 4) + 1 : 0;
-                const int ntw = wave_max4(nt);
+                // chunks of G consecutive disparities from lo
+                const int nt = act ? (hi - lo) / G + 1 : 0;
+                const int ntw = group_max<G>(nt);
                 if (ntw == 0)
                     continue;                                  // uniform over the wave
-                const int qb = (cur * AH2_NG + grp) * spad;
-                const int pb = ((cur ^ 1) * AH2_NG + grp) * spad;
+                const int qb = (cur * NGG + grp) * spad;
+                const int pb = ((cur ^ 1) * NGG + grp) * spad;
                 const int cap = started ? mq + p2 : LBIG;
                 const int sub = started ? mq : 0;
                 const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
@@ -1404,7 +1405,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 int rmin = LBIG;
                 bool diff = false;
                 for (int j = 0; j < ntw; j++) {
-                    const int d = lo + AV_G * j + lane;
+                    const int d = lo + G * j + lane;
                     const bool live = j < nt && d <= hi;
                     const int dd = min(d, D);
                     const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
@@ -1419,7 +1420,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                     const int L = live ? c + best - sub : LBIG;
                     if (MODE == HS_FIX) {
                         // lane i of trajectory A sits 16 lanes below lane i of B
-                        const int other = __shfl_xor(L, AV_G, 64);
+                        const int other = __shfl_xor(L, G, 64);
                         diff = diff || (live && other != L);
                     }
                     if (live) {
@@ -1432,13 +1433,13 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                     }
                     rmin = min(rmin, L);
                 }
-                const int m = row_min16(rmin);
+                const int m = group_min<G>(rmin);
                 if (act) {
                     mq = m;
                     loq = lo;
                     hiq = hi;
                     started = true;
-                    if (MODE != HS_SPEC && row_min16(diff ? 0 : 1) == 1)
+                    if (MODE != HS_SPEC && group_min<G>(diff ? 0 : 1) == 1)
                         done = true;   // stored losses agree from here on
                 }
                 cur ^= 1;
@@ -1529,20 +1530,21 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
         const int seg = g.hseg;
         const int nseg = (g.W + seg - 1) / seg;
         const size_t lds2 = agg_h2_lds(g.D);
-        hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC>, lds2);
+        constexpr int HG = 16, NGG = AH2_T / HG;   // lanes per scanline, scanlines per block
+        hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC, HG>, lds2);
         if (e == hipSuccess)
-            e = allow_lds((const void *)k_agg_h2<HS_FIX>, lds2);
+            e = allow_lds((const void *)k_agg_h2<HS_FIX, HG>, lds2);
         if (e == hipSuccess)
-            e = allow_lds((const void *)k_agg_h2<HS_SEQ>, lds2);
+            e = allow_lds((const void *)k_agg_h2<HS_SEQ, HG>, lds2);
         if (e != hipSuccess)
             return e;
-        hipLaunchKernelGGL((k_agg_h2<HS_SPEC>), dim3((g.H + AH2_NG - 1) / AH2_NG, nseg, nh), dim3(AH2_T), lds2, s,
+        hipLaunchKernelGGL((k_agg_h2<HS_SPEC, HG>), dim3((g.H + NGG - 1) / NGG, nseg, nh), dim3(AH2_T), lds2, s,
                            hv, seg, nseg);
         if (nseg > 1)
-            hipLaunchKernelGGL((k_agg_h2<HS_FIX>), dim3((g.H + AH2_NG / 2 - 1) / (AH2_NG / 2), nseg - 1, nh),
+            hipLaunchKernelGGL((k_agg_h2<HS_FIX, HG>), dim3((g.H + NGG / 2 - 1) / (NGG / 2), nseg - 1, nh),
                                dim3(AH2_T), lds2, s, hv, seg, nseg);
         if (nseg > 2)
-            hipLaunchKernelGGL((k_agg_h2<HS_SEQ>), dim3((g.H + AH2_NG - 1) / AH2_NG, 1, nh), dim3(AH2_T), lds2, s,
+            hipLaunchKernelGGL((k_agg_h2<HS_SEQ, HG>), dim3((g.H + NGG - 1) / NGG, 1, nh), dim3(AH2_T), lds2, s,
                                hv, seg, nseg);
         return hipGetLastError();
     }
