@@ -1244,6 +1244,9 @@ template <int MODE, int G>
 __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
 {
     constexpr int NGG = AH2_T / G;                          // groups of G lanes per block
+    // the horizontal stage is the longer of the two concurrent aggregation
+    // streams: its waves win issue arbitration against the vertical kernel's
+    __builtin_amdgcn_s_setprio(1);
     constexpr int NC = MODE == HS_FIX ? NGG / 2 : NGG;       // scanlines per block
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
