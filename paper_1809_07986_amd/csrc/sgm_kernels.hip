@@ -1516,6 +1516,32 @@ int count_horizontal_paths(const Geometry &g)
     return n;
 }
 
+// segmented scanlines: speculative pass, fix-up pass, cleanup pass
+template <int HG>
+static hipError_t launch_agg_h2(const Geometry &g, const AggArgs &hv, int nh, hipStream_t s)
+{
+    constexpr int NGG = AH2_T / HG;   // scanlines per block
+    const int seg = g.hseg;
+    const int nseg = (g.W + seg - 1) / seg;
+    const size_t lds2 = agg_h2_lds(g.D);
+    hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC, HG>, lds2);
+    if (e == hipSuccess)
+        e = allow_lds((const void *)k_agg_h2<HS_FIX, HG>, lds2);
+    if (e == hipSuccess)
+        e = allow_lds((const void *)k_agg_h2<HS_SEQ, HG>, lds2);
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_agg_h2<HS_SPEC, HG>), dim3((g.H + NGG - 1) / NGG, nseg, nh), dim3(AH2_T), lds2, s, hv,
+                       seg, nseg);
+    if (nseg > 1)
+        hipLaunchKernelGGL((k_agg_h2<HS_FIX, HG>), dim3((g.H + NGG / 2 - 1) / (NGG / 2), nseg - 1, nh),
+                           dim3(AH2_T), lds2, s, hv, seg, nseg);
+    if (nseg > 2)
+        hipLaunchKernelGGL((k_agg_h2<HS_SEQ, HG>), dim3((g.H + NGG - 1) / NGG, 1, nh), dim3(AH2_T), lds2, s, hv,
+                           seg, nseg);
+    return hipGetLastError();
+}
+
 hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s)
 {
     AggArgs hv, vv;
@@ -1529,28 +1555,8 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
     bool segmented = !dense && g.D > 64 && g.D <= 128;
     if (!dense && g.halt)
         segmented = !segmented;
-    if (segmented) {
-        const int seg = g.hseg;
-        const int nseg = (g.W + seg - 1) / seg;
-        const size_t lds2 = agg_h2_lds(g.D);
-        constexpr int HG = 16, NGG = AH2_T / HG;   // lanes per scanline, scanlines per block
-        hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC, HG>, lds2);
-        if (e == hipSuccess)
-            e = allow_lds((const void *)k_agg_h2<HS_FIX, HG>, lds2);
-        if (e == hipSuccess)
-            e = allow_lds((const void *)k_agg_h2<HS_SEQ, HG>, lds2);
-        if (e != hipSuccess)
-            return e;
-        hipLaunchKernelGGL((k_agg_h2<HS_SPEC, HG>), dim3((g.H + NGG - 1) / NGG, nseg, nh), dim3(AH2_T), lds2, s,
-                           hv, seg, nseg);
-        if (nseg > 1)
-            hipLaunchKernelGGL((k_agg_h2<HS_FIX, HG>), dim3((g.H + NGG / 2 - 1) / (NGG / 2), nseg - 1, nh),
-                               dim3(AH2_T), lds2, s, hv, seg, nseg);
-        if (nseg > 2)
-            hipLaunchKernelGGL((k_agg_h2<HS_SEQ, HG>), dim3((g.H + NGG - 1) / NGG, 1, nh), dim3(AH2_T), lds2, s,
-                               hv, seg, nseg);
-        return hipGetLastError();
-    }
+    if (segmented)
+        return g.D > 128 ? launch_agg_h2<32>(g, hv, nh, s) : launch_agg_h2<16>(g, hv, nh, s);
     size_t lds = agg_h_lds(g.W);
     dim3 grd(g.H, nh);
     if (g.D <= 64)
