@@ -134,6 +134,20 @@ def test_shapes_paths_and_census(W, H, D, mask, cw, ch):
     _check_match(g, left, right, prm, lo, hi, f"shape-full-{W}x{H}x{D}")
 
 
+@pytest.mark.parametrize("W,H,D", [(4096, 24, 128), (16, 2048, 100)])
+def test_largest_width_and_tall_images(W, H, D):
+    # the widest image the library takes (most horizontal segments, longest
+    # diagonals) and a tall narrow one (the longest vertical chains)
+    _say(f"case: extreme shape {W}x{H}x{D}")
+    rng = np.random.default_rng(W + H)
+    left = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    right = np.roll(left, -4, axis=1)
+    g = sgmk.ReducedSGM(W, H, D, f=100.0)
+    prm = O.Params(W, H, D, f=100.0)
+    lo, hi = synth.random_windows(rng, H, W, D, max_width=12, full_frac=0.05)
+    _check_match(g, left, right, prm, lo, hi, f"extreme-{W}x{H}x{D}", paths=False)
+
+
 def test_pitched_images():
     seq = synth.make_sequence("tiny")
     H, W = seq.cam.height, seq.cam.width
