@@ -659,8 +659,13 @@ template <int G>
 __device__ __forceinline__ int group_min(int v)
 {
     v = row_min16(v);
-    if (G == 32)
-        v = min(v, __shfl_xor(v, 16, 64));
+    if (G == 32) {
+        // two groups per wave: combine the row minima with scalar reads
+        // (a cross-lane shuffle would take an LDS round trip)
+        const int a = min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16));
+        const int b = min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48));
+        v = (threadIdx.x & 32) ? b : a;
+    }
     if (G == 64) {
         int a = __builtin_amdgcn_readlane(v, 0), b = __builtin_amdgcn_readlane(v, 16);
         int c = __builtin_amdgcn_readlane(v, 32), d = __builtin_amdgcn_readlane(v, 48);
