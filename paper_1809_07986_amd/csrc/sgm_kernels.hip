@@ -1172,14 +1172,15 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
                 const int a0 = tq <= spanq ? v0 : LBIG;
                 const int am = tq - 1u <= spanq ? vm : LBIG;
                 const int ap = tq + 1u <= spanq ? vp : LBIG;
-                const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
+                // branch-free: the terms are read for every lane and masked
+                const int best = min(min(a0, cap), min(am, ap) + p1) & -(int)started;
                 const int pc = __popcll(e.cl ^ crv);
                 const int c = dd > x ? nbits : pc;
                 const int L = live ? c + best - sub : LBIG;
-                if (live) {
-                    sbuf[pb + dd + 1] = (uint16_t)L;
+                // idle lanes write LBIG into slots outside the window (masked when read)
+                sbuf[pb + dd + 1] = (uint16_t)L;
+                if (live)
                     lrk[e.off + (uint32_t)(dd - lo)] = (uint8_t)L;
-                }
                 rmin = min(rmin, L);
             }
             const int m = group_min<G>(rmin);
@@ -1422,20 +1423,22 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                     const int a0 = tq <= spanq ? v0 : LBIG;
                     const int am = tq - 1u <= spanq ? vm : LBIG;
                     const int ap = tq + 1u <= spanq ? vp : LBIG;
-                    const int best = started ? min(min(a0, cap), min(am, ap) + p1) : 0;
+                    // branch-free: the terms are read for every lane and masked
+                    const int best = min(min(a0, cap), min(am, ap) + p1) & -(int)started;
                     const int pc = __popcll(e.cl ^ crv);
                     const int c = dd > x ? nbits : pc;
                     const int L = live ? c + best - sub : LBIG;
                     if (MODE == HS_FIX) {
-                        // lane i of trajectory A sits 16 lanes below lane i of B
+                        // lane i of trajectory A sits G lanes below lane i of B
                         const int other = __shfl_xor(L, G, 64);
                         diff = diff || (live && other != L);
                     }
+                    // idle lanes write LBIG into slots outside the window (masked when read)
+                    sbuf[pb + dd + 1] = (uint16_t)L;
                     if (live) {
                         uint8_t *dst = lrk + e.off + (uint32_t)(dd - lo);
                         if (MODE == HS_SEQ)
                             diff = diff || (*dst != (uint8_t)L);
-                        sbuf[pb + dd + 1] = (uint16_t)L;
                         if (traj_a)
                             *dst = (uint8_t)L;
                     }
