@@ -94,6 +94,8 @@ def test_planted_objects():
     (3, dict(thresh=4, max_detections=60)),          # more windows fire than are kept
     (4, dict(sizes=((16, 16), (24, 12), (9, 31)), top=0, min_area=300)),
     (5, dict(thresh=0, max_detections=400, min_area=0)),   # every window fires
+    (6, dict(thresh=0, max_detections=500, min_area=0, merge_iou=0.1)),   # large groups, greedy per wave
+    (7, dict(thresh=2, merge_iou=0.05, sizes=((12, 12), (20, 20), (20, 36)), min_area=100)),
 ])
 def test_noisy_scenes(seed, kw):
     W, H = 333, 170
