@@ -1133,37 +1133,38 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
     issue(0);
     commit(0);
     __syncthreads();
+    // state buffers: this chain's slots in buffer 0 and the distance to buffer 1
+    const int sb0 = grp * spad, sdel = AV_NG * spad;
     int cur = 0;                    // state buffer holding L_r of the previous pixel
     int mq = 0, loq = 0, hiq = -1;  // its minimum and window (empty before the first pixel)
-    bool started = false;
+    int started = 0;                // all ones once the chain has had a pixel
+    int x = kc;                     // column of the chain's pixel on sweep row t: kc + rx*t
     const int nbt = (H + AV_B - 1) / AV_B;
     for (int bt = 0; bt < nbt; bt++) {
         issue(bt + 1);
         const uint64_t *cb = cbuf + (size_t)(bt & 1) * AV_B * span;
         const MetaEntry *mb = mbuf + (bt & 1) * AV_B * AV_NG;
         const int rows = min(AV_B, H - bt * AV_B);
-        for (int r = 0; r < rows; r++) {
-            const int t = bt * AV_B + r;
-            const int x = kc + rx * t;
-            const bool act = chain_ok && x >= 0 && x < W;   // uniform per group
+        for (int r = 0; r < rows; r++, x += rx) {
+            const bool act = chain_ok && (unsigned)x < (unsigned)W;   // uniform per group
             const MetaEntry e = mb[r * AV_NG + grp];
             const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
             // chunks of G consecutive disparities from lo
             const int nt = act ? (hi - lo) / G + 1 : 0;
-            const int ntw = group_max<G>(nt);
-            if (ntw == 0)
-                continue;                                  // uniform over the wave
-            const int qb = (cur * AV_NG + grp) * spad;     // previous pixel's L_r (slot d + 1)
-            const int pb = ((cur ^ 1) * AV_NG + grp) * spad;
-            const int cap = started ? mq + p2 : LBIG;      // the P2 term (none on the first pixel)
-            const int sub = started ? mq : 0;
+            if (__ballot(nt > 0) == 0)
+                continue;                                  // no chain of the wave is on the image
+            // most steps fit one chunk in every chain; the count is reduced only otherwise
+            const int ntw = __ballot(nt > 1) ? group_max<G>(nt) : 1;
+            const int qb = sb0 + (cur ? sdel : 0);         // previous pixel's L_r (slot d + 1)
+            const int pb = sb0 + (cur ? 0 : sdel);
+            // before the first pixel every term is masked off and mq is 0
+            const int cap = mq + p2;                       // the P2 term
             const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
             const uint64_t *crow = cb + (size_t)r * span;
-            const int cbase = x - span_x0(t);
+            const int cbase = grp + D - 1;                 // the chain's column in the staged span
             int rmin = LBIG;
-            for (int j = 0; j < ntw; j++) {
+            auto chunk = [&](int j, bool live) {
                 const int d = lo + G * j + lane;
-                const bool live = j < nt && d <= hi;
                 const int dd = min(d, D);                  // keeps idle lanes inside the chain's slots
                 // unconditional reads; out-of-window terms become LBIG (absent)
                 const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
@@ -1173,22 +1174,25 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
                 const int am = tq - 1u <= spanq ? vm : LBIG;
                 const int ap = tq + 1u <= spanq ? vp : LBIG;
                 // branch-free: the terms are read for every lane and masked
-                const int best = min(min(a0, cap), min(am, ap) + p1) & -(int)started;
+                const int best = min(min(a0, cap), min(am, ap) + p1) & started;
                 const int pc = __popcll(e.cl ^ crv);
                 const int c = dd > x ? nbits : pc;
-                const int L = live ? c + best - sub : LBIG;
+                const int L = live ? c + best - mq : LBIG;
                 // idle lanes write LBIG into slots outside the window (masked when read)
                 sbuf[pb + dd + 1] = (uint16_t)L;
                 if (live)
                     lrk[e.off + (uint32_t)(dd - lo)] = (uint8_t)L;
                 rmin = min(rmin, L);
-            }
+            };
+            chunk(0, act && lo + lane <= hi);
+            for (int j = 1; j < ntw; j++)
+                chunk(j, j < nt && lo + G * j + lane <= hi);
             const int m = group_min<G>(rmin);
             if (act) {
                 mq = m;
                 loq = lo;
                 hiq = hi;
-                started = true;
+                started = -1;
             }
             cur ^= 1;
             wave_lds_sync();   // this step's state writes precede the next step's reads
@@ -1333,9 +1337,11 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
         }
     };
 
+    // state buffers: this group's slots in buffer 0 and the distance to buffer 1
+    const int sb0 = grp * spad, sdel = NGG * spad;
     int cur = 0;                    // state buffer holding L_r of the previous pixel
     int mq = 0, loq = 0, hiq = -1;  // its minimum and window
-    bool started = false;
+    int started = 0;                // all ones once the trajectory has a state (mq is 0 before)
     bool done = false;              // the trajectory has met the stored losses
     bool ran = false;               // HS_SEQ: the previous segment was recomputed to its end
     const int s_first = MODE == HS_SPEC ? (int)blockIdx.y : MODE == HS_FIX ? (int)blockIdx.y + 1 : 2;
@@ -1361,7 +1367,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
             const int nt = load ? hi / G - lo / G + 1 : 0;
             const int ntw = group_max<G>(nt);
-            const int qb = (cur * NGG + grp) * spad;
+            const int qb = sb0 + (cur ? sdel : 0);
             int rmin = LBIG;
             for (int j = 0; j < ntw; j++) {
                 const int d = (lo / G) * G + G * j + lane;
@@ -1376,10 +1382,10 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 mq = m;
                 loq = lo;
                 hiq = hi;
-                started = true;
+                started = -1;
             }
             if (MODE == HS_FIX && !traj_a)
-                started = false;    // trajectory B restarts like HS_SPEC
+                started = 0;        // trajectory B restarts like HS_SPEC (it never loads: mq is 0)
             wave_lds_sync();
         }
         done = !active;
@@ -1402,20 +1408,20 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
                 // chunks of G consecutive disparities from lo
                 const int nt = act ? (hi - lo) / G + 1 : 0;
-                const int ntw = group_max<G>(nt);
-                if (ntw == 0)
-                    continue;                                  // uniform over the wave
-                const int qb = (cur * NGG + grp) * spad;
-                const int pb = ((cur ^ 1) * NGG + grp) * spad;
-                const int cap = started ? mq + p2 : LBIG;
-                const int sub = started ? mq : 0;
+                if (__ballot(nt > 0) == 0)
+                    continue;                                  // no group of the wave is working
+                // most steps fit one chunk in every group; the count is reduced only otherwise
+                const int ntw = __ballot(nt > 1) ? group_max<G>(nt) : 1;
+                const int qb = sb0 + (cur ? sdel : 0);
+                const int pb = sb0 + (cur ? 0 : sdel);
+                // before the first pixel every term is masked off and mq is 0
+                const int cap = mq + p2;
                 const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
                 const int cbase = x - cx0;
                 int rmin = LBIG;
                 bool diff = false;
-                for (int j = 0; j < ntw; j++) {
+                auto chunk = [&](int j, bool live) {
                     const int d = lo + G * j + lane;
-                    const bool live = j < nt && d <= hi;
                     const int dd = min(d, D);
                     const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
                     const uint64_t crv = crow[max(cbase - dd, 0)];
@@ -1424,10 +1430,10 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                     const int am = tq - 1u <= spanq ? vm : LBIG;
                     const int ap = tq + 1u <= spanq ? vp : LBIG;
                     // branch-free: the terms are read for every lane and masked
-                    const int best = min(min(a0, cap), min(am, ap) + p1) & -(int)started;
+                    const int best = min(min(a0, cap), min(am, ap) + p1) & started;
                     const int pc = __popcll(e.cl ^ crv);
                     const int c = dd > x ? nbits : pc;
-                    const int L = live ? c + best - sub : LBIG;
+                    const int L = live ? c + best - mq : LBIG;
                     if (MODE == HS_FIX) {
                         // lane i of trajectory A sits G lanes below lane i of B
                         const int other = __shfl_xor(L, G, 64);
@@ -1443,13 +1449,16 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                             *dst = (uint8_t)L;
                     }
                     rmin = min(rmin, L);
-                }
+                };
+                chunk(0, act && lo + lane <= hi);
+                for (int j = 1; j < ntw; j++)
+                    chunk(j, j < nt && lo + G * j + lane <= hi);
                 const int m = group_min<G>(rmin);
                 if (act) {
                     mq = m;
                     loq = lo;
                     hiq = hi;
-                    started = true;
+                    started = -1;
                     if (MODE != HS_SPEC && group_min<G>(diff ? 0 : 1) == 1)
                         done = true;   // stored losses agree from here on
                 }
