@@ -1056,12 +1056,13 @@ __host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
            (size_t)2 * NG * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
-// NG chains per block (NG / 4 waves), B rows per staged batch
-template <int NG, int B, int G>
+// NG chains per block (NG / 4 waves), B rows per staged batch, D <= MAXD
+template <int NG, int B, int G, int MAXD>
 __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
 {
     constexpr int AV_NG = NG, AV_B = B, AV_T = NG * G;
-    constexpr int AV_MAXCR = (AV_B * (AV_NG + kMaxDisp - 1) + AV_T - 1) / AV_T;   // per thread
+    // staged census loads per thread, sized for the largest D of the instance
+    constexpr int AV_MAXCR = (AV_B * (AV_NG + MAXD - 1) + AV_T - 1) / AV_T;
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
     const int span = AV_NG + D - 1;
@@ -1145,9 +1146,12 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
         const uint64_t *cb = cbuf + (size_t)(bt & 1) * AV_B * span;
         const MetaEntry *mb = mbuf + (bt & 1) * AV_B * AV_NG;
         const int rows = min(AV_B, H - bt * AV_B);
+        MetaEntry en = mb[grp];                        // metadata of the batch's first row
         for (int r = 0; r < rows; r++, x += rx) {
             const bool act = chain_ok && (unsigned)x < (unsigned)W;   // uniform per group
-            const MetaEntry e = mb[r * AV_NG + grp];
+            const MetaEntry e = en;
+            // the next row's metadata is read a step ahead: its LDS latency overlaps this step
+            en = mb[min(r + 1, rows - 1) * AV_NG + grp];
             const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
             // chunks of G consecutive disparities from lo
             const int nt = act ? (hi - lo) / G + 1 : 0;
@@ -1206,13 +1210,15 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
 // along some columns (the left border, vertical edges) and would otherwise
 // make a few blocks take twice as long as the rest; diagonal chains cross
 // such columns and keep 16 lanes (16 per block).
+// (MAXD bounds D: the staging registers of D <= 128 are half those of 256).
+template <int MAXD>
 __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 {
     const int pi = blockIdx.y;
     if (a.rx[pi] == 0)
-        agg_v2_chains<8, 8, 32>(a, pi);
+        agg_v2_chains<8, 8, 32, MAXD>(a, pi);
     else
-        agg_v2_chains<16, 8, 16>(a, pi);
+        agg_v2_chains<16, 8, 16, MAXD>(a, pi);
 }
 
 // ---- horizontal paths: 256 / G scanlines per block, LDS state, segments ----
@@ -1238,7 +1244,6 @@ __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 
 enum { HS_SPEC = 0, HS_FIX = 1, HS_SEQ = 2 };
 constexpr int AH2_NG = 16, AH2_T = AH2_NG * AV_G, AH2_B = 8;
-constexpr int AH2_MAXCR = (AH2_NG * (kMaxDisp + AH2_B - 1) + AH2_T - 1) / AH2_T;   // per thread
 constexpr int AH2_MAXSEG = kHMaxSeg;
 static_assert(AH2_MAXSEG * 48 >= 4096, "segments of the widest image");
 
@@ -1258,6 +1263,9 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
     // streams: its waves win issue arbitration against the vertical kernel's
     __builtin_amdgcn_s_setprio(1);
     constexpr int NC = MODE == HS_FIX ? NGG / 2 : NGG;       // scanlines per block
+    // staged census loads per thread: 16-lane groups serve D <= 128, 32-lane groups D <= 256
+    constexpr int MAXD = G == 16 ? 128 : kMaxDisp;
+    constexpr int MAXCR = (NGG * (MAXD + AH2_B - 1) + AH2_T - 1) / AH2_T;
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
     const int span = agg_h2_span(D), spad = agg_v2_spad(D);
@@ -1292,13 +1300,13 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             return;
     }
 
-    uint64_t rc[AH2_MAXCR];
+    uint64_t rc[MAXCR];
     uint64_t rmcl;
     uint32_t rmoff, rmwin;
     auto issue = [&](int tb, int tend) {
         const int sx0 = span_x0(tb);
 #pragma unroll
-        for (int i = 0; i < AH2_MAXCR; i++) {
+        for (int i = 0; i < MAXCR; i++) {
             const int e = threadIdx.x + i * AH2_T;
             const int c = e / span, col = e - c * span;
             const int yy = y0 + c, xx = sx0 + col;
@@ -1323,7 +1331,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
     auto commit = [&](int buf) {
         uint64_t *cb = cbuf + (size_t)buf * NGG * span;
 #pragma unroll
-        for (int i = 0; i < AH2_MAXCR; i++) {
+        for (int i = 0; i < MAXCR; i++) {
             const int e = threadIdx.x + i * AH2_T;
             if (e < NC * span)
                 cb[e] = rc[i];
@@ -1401,10 +1409,13 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             const MetaEntry *mb = mbuf + (bt & 1) * AH2_B * NGG;
             const int cx0 = span_x0(tb);
             const int rows = min(AH2_B, t1 - tb);
+            MetaEntry en = mb[cg];                          // metadata of the batch's first step
             for (int r = 0; r < rows; r++) {
                 const int x = colx(tb + r);
                 const bool act = row_ok && !done;            // uniform per group (and per scanline in HS_FIX)
-                const MetaEntry e = mb[r * NC + cg];
+                const MetaEntry e = en;
+                // the next step's metadata is read a step ahead: its LDS latency overlaps this step
+                en = mb[min(r + 1, rows - 1) * NC + cg];
                 const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
                 // chunks of G consecutive disparities from lo
                 const int nt = act ? (hi - lo) / G + 1 : 0;
@@ -1538,6 +1549,8 @@ template <int HG>
 static hipError_t launch_agg_h2(const Geometry &g, const AggArgs &hv, int nh, hipStream_t s)
 {
     constexpr int NGG = AH2_T / HG;   // scanlines per block
+    if (HG == 16 && g.D > 128)
+        return hipErrorInvalidValue;  // 16-lane groups stage at most D = 128
     const int seg = g.hseg;
     const int nseg = (g.W + seg - 1) / seg;
     const size_t lds2 = agg_h2_lds(g.D);
@@ -1608,7 +1621,10 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
     int nbx = 0;
     for (int i = 0; i < nv; i++)
         nbx = max(nbx, vv.rx[i] == 0 ? (g.W + 7) / 8 : (g.W + g.H - 1 + 15) / 16);
-    hipLaunchKernelGGL(k_agg_v2, dim3(nbx, nv), dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
+    if (g.D <= 128)
+        hipLaunchKernelGGL(k_agg_v2<128>, dim3(nbx, nv), dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
+    else
+        hipLaunchKernelGGL(k_agg_v2<kMaxDisp>, dim3(nbx, nv), dim3(256), agg_v2_lds(g.D, 16, 8), s, vv);
     return hipGetLastError();
 }
 
