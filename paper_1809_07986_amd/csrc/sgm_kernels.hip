@@ -1239,20 +1239,25 @@ __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 //           comparing with the stored losses until they agree.
 // When no segment s-1 is flagged, the end of s-1 stored after HS_SPEC is
 // exact (by induction from segment 0), so HS_FIX made segment s exact.
-// Each block stages, per 8-step batch, its scanlines' right census over the
-// D+7 columns the batch can reach, and the pixels' metadata.
+// Each block keeps its scanlines' right census in LDS rings indexed by
+// absolute column (column c in slot c mod R): a segment starts by staging the
+// D+7 columns its first 8-step batch can reach, and each later batch adds the
+// 8 columns it reaches beyond the previous one.  The pixels' metadata is
+// staged per batch.
 
 enum { HS_SPEC = 0, HS_FIX = 1, HS_SEQ = 2 };
 constexpr int AH2_NG = 16, AH2_T = AH2_NG * AV_G, AH2_B = 8;
 constexpr int AH2_MAXSEG = kHMaxSeg;
 static_assert(AH2_MAXSEG * 48 >= 4096, "segments of the widest image");
 
-__host__ __device__ constexpr int agg_h2_span(int D) { return D + AH2_B - 1; }
+// census ring length per scanline: a power of two >= D + 2B - 1 (a batch's
+// reach plus the next batch's new columns); 16-lane groups serve D <= 128
+__host__ __device__ constexpr int agg_h2_ring(int G) { return G == 16 ? 256 : 512; }
 
-__host__ __device__ constexpr size_t agg_h2_lds(int D)
+__host__ __device__ constexpr size_t agg_h2_lds(int D, int G)
 {
-    return (size_t)2 * AH2_NG * agg_h2_span(D) * 8 + (size_t)2 * AH2_B * AH2_NG * sizeof(MetaEntry) +
-           (size_t)2 * AH2_NG * agg_v2_spad(D) * sizeof(uint16_t);
+    return (size_t)(AH2_T / G) * agg_h2_ring(G) * 8 + (size_t)2 * AH2_B * (AH2_T / G) * sizeof(MetaEntry) +
+           (size_t)2 * (AH2_T / G) * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
 template <int MODE, int G>
@@ -1268,9 +1273,11 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
     constexpr int MAXCR = (NGG * (MAXD + AH2_B - 1) + AH2_T - 1) / AH2_T;
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W, H = a.H, D = a.D;
-    const int span = agg_h2_span(D), spad = agg_v2_spad(D);
-    uint64_t *cbuf = (uint64_t *)smem;                                               // [2][NC][span]
-    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * NGG * span * 8);              // [2][B][NC]
+    const int spad = agg_v2_spad(D);
+    constexpr int R = agg_h2_ring(G);
+    static_assert(R >= MAXD + 2 * AH2_B - 1, "ring holds a batch's reach and the next batch's columns");
+    uint64_t *ring = (uint64_t *)smem;                                               // [NC][R]
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)NGG * R * 8);                     // [2][B][NC]
     uint16_t *sbuf = (uint16_t *)((uint8_t *)mbuf + (size_t)2 * AH2_B * NGG * sizeof(MetaEntry));
     const int pi = blockIdx.z;
     const int k = a.slot[pi];
@@ -1300,42 +1307,59 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             return;
     }
 
-    uint64_t rc[MAXCR];
-    uint64_t rmcl;
-    uint32_t rmoff, rmwin;
-    auto issue = [&](int tb, int tend) {
-        const int sx0 = span_x0(tb);
+    // segment start: every census column the first batch (steps from tb) reaches
+    auto fill = [&](int tb) {
+        const int n = D + AH2_B - 1, c0 = span_x0(tb);
+        uint64_t rc[MAXCR];
 #pragma unroll
         for (int i = 0; i < MAXCR; i++) {
             const int e = threadIdx.x + i * AH2_T;
-            const int c = e / span, col = e - c * span;
-            const int yy = y0 + c, xx = sx0 + col;
-            const bool ok = c < NC && yy < H && xx >= 0 && xx < W;
-            const size_t idx = ok ? (size_t)yy * W + xx : 0;
+            const int c = e / n, col = c0 + (e - c * n);
+            const bool ok = c < NC && y0 + c < H && col >= 0 && col < W;
+            const size_t idx = ok ? (size_t)(y0 + c) * W + col : 0;
             const uint64_t v = a.cr[idx];
             rc[i] = ok ? v : 0ull;
         }
-        {
-            const int e = threadIdx.x;
-            const int r = e / NC, c = e - r * NC;
-            const int t = tb + r, yy = y0 + c;
-            const bool ok = e < AH2_B * NC && t < tend && yy < H;
-            const int pix = ok ? yy * W + colx(t) : 0;
-            const uint64_t vcl = a.cl[pix];
-            const uint32_t voff = a.off[pix], vwin = a.win[pix];
-            rmcl = ok ? vcl : 0ull;
-            rmoff = ok ? voff : 0u;
-            rmwin = ok ? vwin : 0u;
-        }
-    };
-    auto commit = [&](int buf) {
-        uint64_t *cb = cbuf + (size_t)buf * NGG * span;
 #pragma unroll
         for (int i = 0; i < MAXCR; i++) {
             const int e = threadIdx.x + i * AH2_T;
-            if (e < NC * span)
-                cb[e] = rc[i];
+            const int c = e / n, col = c0 + (e - c * n);
+            if (c < NC)
+                ring[c * R + (col & (R - 1))] = rc[i];
         }
+    };
+    // later batches: the B columns the batch from tn reaches beyond the
+    // previous one (rx > 0: tn.., rx < 0: its lowest B), one per thread, and
+    // the batch's metadata; loaded a batch ahead and written at its end
+    const int nc = threadIdx.x / AH2_B, nk = threadIdx.x % AH2_B;
+    auto new_col = [&](int tn) { return (rx > 0 ? tn : span_x0(tn)) + nk; };
+    uint64_t rn;
+    uint64_t rmcl;
+    uint32_t rmoff, rmwin;
+    auto issue_cols = [&](int tn) {
+        const int col = new_col(tn);
+        const bool ok = nc < NC && y0 + nc < H && col >= 0 && col < W;
+        const size_t idx = ok ? (size_t)(y0 + nc) * W + col : 0;
+        const uint64_t v = a.cr[idx];
+        rn = ok ? v : 0ull;
+    };
+    auto issue_meta = [&](int tb, int tend) {
+        const int e = threadIdx.x;
+        const int r = e / NC, c = e - r * NC;
+        const int t = tb + r, yy = y0 + c;
+        const bool ok = e < AH2_B * NC && t < tend && yy < H;
+        const int pix = ok ? yy * W + colx(t) : 0;
+        const uint64_t vcl = a.cl[pix];
+        const uint32_t voff = a.off[pix], vwin = a.win[pix];
+        rmcl = ok ? vcl : 0ull;
+        rmoff = ok ? voff : 0u;
+        rmwin = ok ? vwin : 0u;
+    };
+    auto commit_cols = [&](int tn) {
+        if (nc < NC)
+            ring[nc * R + (new_col(tn) & (R - 1))] = rn;
+    };
+    auto commit_meta = [&](int buf) {
         if (threadIdx.x < AH2_B * NC) {
             MetaEntry m;
             m.cl = rmcl;
@@ -1397,17 +1421,19 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
             wave_lds_sync();
         }
         done = !active;
-        issue(t0, t1);
-        commit(0);
+        issue_meta(t0, t1);
+        fill(t0);
+        commit_meta(0);
         __syncthreads();
         const int nbt = (t1 - t0 + AH2_B - 1) / AH2_B;
         for (int bt = 0; bt < nbt; bt++) {
             const int tb = t0 + bt * AH2_B;
-            if (bt + 1 < nbt)
-                issue(tb + AH2_B, t1);
-            const uint64_t *crow = cbuf + (size_t)(bt & 1) * NGG * span + (size_t)cg * span;
+            if (bt + 1 < nbt) {
+                issue_cols(tb + AH2_B);
+                issue_meta(tb + AH2_B, t1);
+            }
+            const uint64_t *crow = ring + (size_t)cg * R;
             const MetaEntry *mb = mbuf + (bt & 1) * AH2_B * NGG;
-            const int cx0 = span_x0(tb);
             const int rows = min(AH2_B, t1 - tb);
             MetaEntry en = mb[cg];                          // metadata of the batch's first step
             for (int r = 0; r < rows; r++) {
@@ -1428,14 +1454,13 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 // before the first pixel every term is masked off and mq is 0
                 const int cap = mq + p2;
                 const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
-                const int cbase = x - cx0;
                 int rmin = LBIG;
                 bool diff = false;
                 auto chunk = [&](int j, bool live) {
                     const int d = lo + G * j + lane;
                     const int dd = min(d, D);
                     const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
-                    const uint64_t crv = crow[max(cbase - dd, 0)];
+                    const uint64_t crv = crow[(x - dd) & (R - 1)];   // right census at column x - d
                     const uint32_t tq = (uint32_t)(dd - loq);
                     const int a0 = tq <= spanq ? v0 : LBIG;
                     const int am = tq - 1u <= spanq ? vm : LBIG;
@@ -1480,8 +1505,10 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 if (!__syncthreads_or(row_ok && !done ? 1 : 0))
                     break;   // every scanline of the block has met the stored losses
             }
-            if (bt + 1 < nbt)
-                commit((bt + 1) & 1);
+            if (bt + 1 < nbt) {
+                commit_cols(tb + AH2_B);
+                commit_meta((bt + 1) & 1);
+            }
             __syncthreads();
         }
         if (MODE == HS_FIX && traj_a && lane == 0 && row_ok)
@@ -1553,7 +1580,7 @@ static hipError_t launch_agg_h2(const Geometry &g, const AggArgs &hv, int nh, hi
         return hipErrorInvalidValue;  // 16-lane groups stage at most D = 128
     const int seg = g.hseg;
     const int nseg = (g.W + seg - 1) / seg;
-    const size_t lds2 = agg_h2_lds(g.D);
+    const size_t lds2 = agg_h2_lds(g.D, HG);
     hipError_t e = allow_lds((const void *)k_agg_h2<HS_SPEC, HG>, lds2);
     if (e == hipSuccess)
         e = allow_lds((const void *)k_agg_h2<HS_FIX, HG>, lds2);
