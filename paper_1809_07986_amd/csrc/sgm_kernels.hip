@@ -1052,7 +1052,7 @@ __host__ __device__ constexpr int agg_v2_spad(int D) { return (D + AV2_PAD + 1) 
 
 __host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
 {
-    return (size_t)2 * B * (NG + D - 1) * 8 + (size_t)2 * B * NG * sizeof(MetaEntry) +
+    return (size_t)B * (NG + D - 1) * 8 + (size_t)B * NG * sizeof(MetaEntry) +
            (size_t)2 * NG * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
@@ -1067,10 +1067,11 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
     const int W = a.W, H = a.H, D = a.D;
     const int span = AV_NG + D - 1;
     const int spad = agg_v2_spad(D);
-    uint64_t *cbuf = (uint64_t *)smem;                                            // [2][B][span]
-    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)2 * AV_B * span * 8);          // [2][B][NG]
-    uint16_t *sbuf = (uint16_t *)(smem + (size_t)2 * AV_B * span * 8 +
-                                  (size_t)2 * AV_B * AV_NG * sizeof(MetaEntry));  // [2][NG][spad]
+    // one staging buffer: a batch's loads wait in registers until every wave has left the previous batch
+    uint64_t *cbuf = (uint64_t *)smem;                                            // [B][span]
+    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)AV_B * span * 8);              // [B][NG]
+    uint16_t *sbuf = (uint16_t *)(smem + (size_t)AV_B * span * 8 +
+                                  (size_t)AV_B * AV_NG * sizeof(MetaEntry));      // [2][NG][spad]
     const int k = a.slot[pi];
     const int rx = a.rx[pi], ry = a.ry[pi];
     const int kmin = a.kmin[pi];
@@ -1115,24 +1116,23 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
             rmwin = ok ? vwin : 0u;
         }
     };
-    auto commit = [&](int buf) {
-        uint64_t *cb = cbuf + (size_t)buf * AV_B * span;
+    auto commit = [&]() {
 #pragma unroll
         for (int i = 0; i < AV_MAXCR; i++) {
             const int e = threadIdx.x + i * AV_T;
             if (e < AV_B * span)
-                cb[e] = rc[i];
+                cbuf[e] = rc[i];
         }
         if (threadIdx.x < AV_B * AV_NG) {
             MetaEntry m;
             m.cl = rmcl;
             m.off = rmoff;
             m.win = rmwin;
-            mbuf[buf * AV_B * AV_NG + threadIdx.x] = m;
+            mbuf[threadIdx.x] = m;
         }
     };
     issue(0);
-    commit(0);
+    commit();
     __syncthreads();
     // state buffers: this chain's slots in buffer 0 and the distance to buffer 1
     const int sb0 = grp * spad, sdel = AV_NG * spad;
@@ -1143,8 +1143,8 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
     const int nbt = (H + AV_B - 1) / AV_B;
     for (int bt = 0; bt < nbt; bt++) {
         issue(bt + 1);
-        const uint64_t *cb = cbuf + (size_t)(bt & 1) * AV_B * span;
-        const MetaEntry *mb = mbuf + (bt & 1) * AV_B * AV_NG;
+        const uint64_t *cb = cbuf;
+        const MetaEntry *mb = mbuf;
         const int rows = min(AV_B, H - bt * AV_B);
         MetaEntry en = mb[grp];                        // metadata of the batch's first row
         for (int r = 0; r < rows; r++, x += rx) {
@@ -1201,7 +1201,8 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
             cur ^= 1;
             wave_lds_sync();   // this step's state writes precede the next step's reads
         }
-        commit((bt + 1) & 1);
+        __syncthreads();   // every wave has left this batch's staging
+        commit();
         __syncthreads();
     }
 }
@@ -1215,6 +1216,9 @@ template <int MAXD>
 __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 {
     const int pi = blockIdx.y;
+    // this kernel runs beside the horizontal passes on a second stream and is
+    // the longer of the two: its waves win issue arbitration
+    __builtin_amdgcn_s_setprio(1);
     if (a.rx[pi] == 0)
         agg_v2_chains<8, 8, 32, MAXD>(a, pi);
     else
@@ -1264,9 +1268,6 @@ template <int MODE, int G>
 __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
 {
     constexpr int NGG = AH2_T / G;                          // groups of G lanes per block
-    // the horizontal stage is the longer of the two concurrent aggregation
-    // streams: its waves win issue arbitration against the vertical kernel's
-    __builtin_amdgcn_s_setprio(1);
     constexpr int NC = MODE == HS_FIX ? NGG / 2 : NGG;       // scanlines per block
     // staged census loads per thread: 16-lane groups serve D <= 128, 32-lane groups D <= 256
     constexpr int MAXD = G == 16 ? 128 : kMaxDisp;
