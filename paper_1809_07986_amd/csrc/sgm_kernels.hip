@@ -1692,13 +1692,25 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        const float *__restrict__ rpix, double *__restrict__ nu_out)
 {
     constexpr int WNG = WTA_T / WG;   // pixels per block
-    __shared__ uint16_t ssum[WNG][kMaxDisp + 8];
+    extern __shared__ uint16_t ssum_lds[];   // [WNG][D + 8] cost sums of each pixel's window
     const int grp = threadIdx.x / WG, lane = threadIdx.x % WG;
     const int t = blockIdx.x * WNG + grp;
     if (t >= N)
         return;   // the whole group leaves together
+    uint16_t *ssum = ssum_lds + (size_t)grp * (D + 8);
     const uint32_t o = off[t];
     const uint32_t wv = win[t];
+    // the correction's inputs are read with the window: their latency overlaps the sums
+    uint8_t fl = 0;
+    double dh = 0.0, pv = 0.0;
+    float rp = 0.0f;
+    if (mode != 2 && lane == 0) {
+        fl = flags[t];
+        dh = dhat[t];
+        pv = pm[t];
+        if (rpix)
+            rp = rpix[t];
+    }
     const int lo = (int)(wv & 255), w = (int)(wv >> 8) + 1, hi = lo + w - 1;
     // each lane sums four consecutive cells of every path from aligned
     // dwords (16-bit halves: even and odd bytes; S <= 8 * 148 < 2^16).
@@ -1721,7 +1733,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
         for (int b = 0; b < 4; b++) {
             const int sl = 4 * q + b - lead;      // slot within the window
             if (sl >= 0 && sl < w) {
-                ssum[grp][sl] = (uint16_t)s4[b];
+                ssum[sl] = (uint16_t)s4[b];
                 if (dbg_sum)
                     dbg_sum[o + sl] = (uint16_t)s4[b];
                 key = min(key, (s4[b] << 9) | (uint32_t)sl);
@@ -1738,18 +1750,16 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     const int ds = lo + slot;
     double dz = (double)ds;
     if (ds - 1 >= lo && ds + 1 <= hi) {
-        const int a = (int)ssum[grp][slot - 1] - s0, b = (int)ssum[grp][slot + 1] - s0;
+        const int a = (int)ssum[slot - 1] - s0, b = (int)ssum[slot + 1] - s0;
         dz = (double)ds + (double)(a - b) / (double)(2 * (a + b));
     }
     dstar_out[t] = ds;
     dz_out[t] = dz;
     if (mode == 2)
         return;
-    const uint8_t fl = flags[t];
-    const double r = rpix ? (double)rpix[t] : cc.r;
+    const double r = rpix ? (double)rp : cc.r;
     bool moving = false;
     double nu = 0.0, S = 0.0;
-    const double dh = dhat[t], pv = pm[t];
     if (fl & SGM_FLAG_PRED) {
         nu = dz - dh;
         S = pv + r;
@@ -1783,12 +1793,14 @@ hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectCon
                               bool debug_sum, const float *rpix, hipStream_t s)
 {
     if (mode == 0)
-        hipLaunchKernelGGL((k_wta_correct<16>), dim3((g.N + 15) / 16), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
+        hipLaunchKernelGGL((k_wta_correct<16>), dim3((g.N + 15) / 16), dim3(WTA_T), (size_t)16 * (g.D + 8) * 2, s,
+                           g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
                        b.nu);
     else
-        hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), 0, s, g.N, g.D, g.npaths, cc,
+        hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), (size_t)32 * (g.D + 8) * 2, s,
+                           g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
                        b.nu);
