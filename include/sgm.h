@@ -179,7 +179,7 @@ int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
 /* Debug switches for the following frames (bit mask, 0 = off):
  *   SGM_DEBUG_STAGES  record the cost and sum stages (slower);
  *   SGM_DEBUG_SHORT_SEGMENTS  cut horizontal scanlines into 48-pixel segments
- *     instead of 96 (results are identical; exercises the segment fix-up);
+ *     instead of 72 (results are identical; exercises the segment fix-up);
  *   SGM_DEBUG_ALT_HORIZONTAL  reduced frames use the other horizontal
  *     aggregation kernel than the one chosen for max_disp (segmented scanlines
  *     for 64 < max_disp <= 128, one wave per scanline otherwise); results are

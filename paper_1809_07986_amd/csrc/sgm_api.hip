@@ -415,7 +415,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     g.D = prm->max_disp;
     g.N = g.W * g.H;
     g.lr_stride = (((size_t)g.N * g.D) + 255) & ~(size_t)255;
-    g.hseg = 96;
+    g.hseg = 72;
     g.halt = false;
     g.cw = prm->census_w;
     g.ch = prm->census_h;
@@ -598,7 +598,7 @@ int sgm_set_debug(sgm_context *ctx, int32_t on)
     if (on & ~(SGM_DEBUG_STAGES | SGM_DEBUG_SHORT_SEGMENTS | SGM_DEBUG_ALT_HORIZONTAL))
         return fail(SGM_EINVAL, "unknown debug bits 0x%x", on);
     ctx->debug = (on & SGM_DEBUG_STAGES) != 0;
-    ctx->g.hseg = (on & SGM_DEBUG_SHORT_SEGMENTS) ? 48 : 96;
+    ctx->g.hseg = (on & SGM_DEBUG_SHORT_SEGMENTS) ? 48 : 72;
     ctx->g.halt = (on & SGM_DEBUG_ALT_HORIZONTAL) != 0;
     return SGM_OK;
 }

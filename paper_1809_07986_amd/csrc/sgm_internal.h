@@ -56,7 +56,7 @@ struct DevBuffers {
 struct Geometry {
     int W, H, D, N;
     size_t lr_stride;          // bytes between the path-loss buffers: N*D rounded up to 256
-    int hseg;                  // horizontal aggregation: pixels per scanline segment (48 or 96)
+    int hseg;                  // horizontal aggregation: pixels per scanline segment (72, or 48 in debug)
     bool halt;                 // reduced frames: the other horizontal kernel than the size-based choice
     int cw, ch, nbits;
     int p1, p2;

@@ -814,8 +814,13 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 }
 
 template <int MAXCH>
-__global__ __launch_bounds__(64) void k_agg_h(AggArgs a)
+__global__ __launch_bounds__(64) void k_agg_h(AggArgs a, int raise_prio)
 {
+    // with ragged windows at D > 128 this is the longer of the two concurrent
+    // aggregation streams: its waves win issue arbitration (with dense
+    // windows the vertical kernel is the longer one)
+    if (raise_prio)
+        __builtin_amdgcn_s_setprio(1);
     constexpr int G = 64;
     extern __shared__ __align__(16) uint8_t smem[];
     const int W = a.W;
@@ -1216,9 +1221,12 @@ template <int MAXD>
 __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 {
     const int pi = blockIdx.y;
-    // this kernel runs beside the horizontal passes on a second stream and is
-    // the longer of the two: its waves win issue arbitration
-    __builtin_amdgcn_s_setprio(1);
+    // this kernel runs beside the horizontal passes on a second stream: at
+    // D <= 128 it is the longer of the two and its waves win issue
+    // arbitration; at larger D the one-wave-per-scanline horizontal kernel is
+    // the longer one and takes the priority instead
+    if (MAXD <= 128)
+        __builtin_amdgcn_s_setprio(1);
     if (a.rx[pi] == 0)
         agg_v2_chains<8, 8, 32, MAXD>(a, pi);
     else
@@ -1617,12 +1625,13 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
         return g.D > 128 ? launch_agg_h2<32>(g, hv, nh, s) : launch_agg_h2<16>(g, hv, nh, s);
     size_t lds = agg_h_lds(g.W);
     dim3 grd(g.H, nh);
+    const int prio = dense ? 0 : 1;
     if (g.D <= 64)
-        hipLaunchKernelGGL((k_agg_h<1>), grd, dim3(64), lds, s, hv);
+        hipLaunchKernelGGL((k_agg_h<1>), grd, dim3(64), lds, s, hv, prio);
     else if (g.D <= 128)
-        hipLaunchKernelGGL((k_agg_h<2>), grd, dim3(64), lds, s, hv);
+        hipLaunchKernelGGL((k_agg_h<2>), grd, dim3(64), lds, s, hv, prio);
     else
-        hipLaunchKernelGGL((k_agg_h<4>), grd, dim3(64), lds, s, hv);
+        hipLaunchKernelGGL((k_agg_h<4>), grd, dim3(64), lds, s, hv, prio);
     return hipGetLastError();
 }
 
