@@ -1036,12 +1036,12 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
 // ---- vertical and diagonal paths, LDS-resident recurrence state ----------
 //
 // Staging as in k_agg_v (NG chains per block, 8-row batches of right census
-// and pixel metadata in LDS), but each chain (a group of G lanes) keeps the
-// previous pixel's L_r in LDS, indexed by absolute disparity, and reads its
-// d-1, d, d+1 terms back masked by that pixel's window.  A step covers the
-// window in chunks of G consecutive disparities from its lower bound; the
-// chunk loop runs to the largest count among the wave's chains, so a narrow
-// step costs one chunk.
+// and pixel metadata in LDS, here in one buffer), but each chain (a group of
+// G lanes) keeps the previous pixel's L_r in LDS, indexed by absolute
+// disparity, and reads its d-1, d, d+1 terms back masked by that pixel's
+// window.  A step covers the window in chunks of G consecutive disparities
+// from its lower bound; the chunk loop runs to the largest count among the
+// wave's chains, so a narrow step costs one chunk.
 
 // max of a group-uniform value over the groups of G lanes of a wave
 template <int G>
@@ -1061,7 +1061,7 @@ __host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
            (size_t)2 * NG * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
-// NG chains per block (NG / 4 waves), B rows per staged batch, D <= MAXD
+// NG chains of G lanes per block (NG * G threads), B rows per staged batch, D <= MAXD
 template <int NG, int B, int G, int MAXD>
 __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
 {
@@ -1709,17 +1709,10 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     uint16_t *ssum = ssum_lds + (size_t)grp * (D + 8);
     const uint32_t o = off[t];
     const uint32_t wv = win[t];
-    // the correction's inputs are read with the window: their latency overlaps the sums
-    uint8_t fl = 0;
-    double dh = 0.0, pv = 0.0;
-    float rp = 0.0f;
-    if (mode != 2 && lane == 0) {
-        fl = flags[t];
-        dh = dhat[t];
-        pv = pm[t];
-        if (rpix)
-            rp = rpix[t];
-    }
+    // the correction's inputs are read with the window (every lane, no branch):
+    // their latency overlaps the sums
+    const uint8_t fl = flags[t];
+    const double dh = dhat[t], pv = pm[t];
     const int lo = (int)(wv & 255), w = (int)(wv >> 8) + 1, hi = lo + w - 1;
     // each lane sums four consecutive cells of every path from aligned
     // dwords (16-bit halves: even and odd bytes; S <= 8 * 148 < 2^16).
@@ -1731,11 +1724,17 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     uint32_t key = 0x7FFFFFFFu;   // above every real key (S << 9 | slot < 2^20)
     for (int q = lane; q < ndw; q += WG) {
         const uint32_t byte0 = a0 + 4u * (uint32_t)q;
+        // the paths' dwords are loaded together (path index clamped, value masked)
+        uint32_t v[kMaxPaths];
+#pragma unroll
+        for (int k = 0; k < kMaxPaths; k++)
+            v[k] = *(const uint32_t *)(lr + (size_t)min(k, npaths - 1) * lr_stride + byte0);
         uint32_t ev = 0, od = 0;
-        for (int k = 0; k < npaths; k++) {
-            const uint32_t v = *(const uint32_t *)(lr + (size_t)k * lr_stride + byte0);
-            ev += v & 0x00FF00FFu;
-            od += (v >> 8) & 0x00FF00FFu;
+#pragma unroll
+        for (int k = 0; k < kMaxPaths; k++) {
+            const uint32_t vm = k < npaths ? v[k] : 0u;
+            ev += vm & 0x00FF00FFu;
+            od += (vm >> 8) & 0x00FF00FFu;
         }
         const uint32_t s4[4] = {ev & 0xFFFFu, od & 0xFFFFu, ev >> 16, od >> 16};
 #pragma unroll
@@ -1766,7 +1765,7 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     dz_out[t] = dz;
     if (mode == 2)
         return;
-    const double r = rpix ? (double)rp : cc.r;
+    const double r = rpix ? (double)rpix[t] : cc.r;
     bool moving = false;
     double nu = 0.0, S = 0.0;
     if (fl & SGM_FLAG_PRED) {
