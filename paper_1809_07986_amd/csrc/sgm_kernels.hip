@@ -302,34 +302,35 @@ __global__ void k_splat_resolve(int N, unsigned long long *__restrict__ zkey, ui
 
 // zooming holes: a target without a winner whose left & right (or upper &
 // lower) neighbours both have winners takes their mean disparity and mean
-// variance; with both pairs, the mean of four (summed left, right, up, down)
-__device__ __forceinline__ void fill_hole(int W, int H, int t, int x, int y, const uint8_t *__restrict__ has,
-                                          const double *__restrict__ dw, const double *__restrict__ pw,
-                                          const uint8_t *__restrict__ rw, uint8_t &pr, double &dv, double &pv,
-                                          uint8_t &rv)
+// variance; with both pairs, the mean of four (summed left, right, up, down).
+// The splat results are read from a tile staged in LDS: entry s is pixel
+// (x, y), its row neighbours are s -/+ 1 and its column neighbours s -/+ ls.
+__device__ __forceinline__ void fill_hole(int W, int H, int s, int ls, int x, int y, const uint8_t *has,
+                                          const double *dw, const double *pw, const uint8_t *rw, uint8_t &pr,
+                                          double &dv, double &pv, uint8_t &rv)
 {
-    pr = has[t];
-    dv = dw[t];
-    pv = pw[t];
-    rv = rw[t];
+    pr = has[s];
+    dv = dw[s];
+    pv = pw[s];
+    rv = rw[s];
     if (pr)
         return;
-    const bool hp = x - 1 >= 0 && x + 1 < W && has[t - 1] && has[t + 1];
-    const bool vp = y - 1 >= 0 && y + 1 < H && has[t - W] && has[t + W];
+    const bool hp = x - 1 >= 0 && x + 1 < W && has[s - 1] && has[s + 1];
+    const bool vp = y - 1 >= 0 && y + 1 < H && has[s - ls] && has[s + ls];
     if (hp && vp) {
-        dv = (((dw[t - 1] + dw[t + 1]) + dw[t - W]) + dw[t + W]) / 4.0;
-        pv = (((pw[t - 1] + pw[t + 1]) + pw[t - W]) + pw[t + W]) / 4.0;
-        rv = rw[t - 1] | rw[t + 1] | rw[t - W] | rw[t + W];
+        dv = (((dw[s - 1] + dw[s + 1]) + dw[s - ls]) + dw[s + ls]) / 4.0;
+        pv = (((pw[s - 1] + pw[s + 1]) + pw[s - ls]) + pw[s + ls]) / 4.0;
+        rv = rw[s - 1] | rw[s + 1] | rw[s - ls] | rw[s + ls];
         pr = 1;
     } else if (hp) {
-        dv = (dw[t - 1] + dw[t + 1]) / 2.0;
-        pv = (pw[t - 1] + pw[t + 1]) / 2.0;
-        rv = rw[t - 1] | rw[t + 1];
+        dv = (dw[s - 1] + dw[s + 1]) / 2.0;
+        pv = (pw[s - 1] + pw[s + 1]) / 2.0;
+        rv = rw[s - 1] | rw[s + 1];
         pr = 1;
     } else if (vp) {
-        dv = (dw[t - W] + dw[t + W]) / 2.0;
-        pv = (pw[t - W] + pw[t + W]) / 2.0;
-        rv = rw[t - W] | rw[t + W];
+        dv = (dw[s - ls] + dw[s + ls]) / 2.0;
+        pv = (pw[s - ls] + pw[s + ls]) / 2.0;
+        rv = rw[s - ls] | rw[s + ls];
         pr = 1;
     }
 }
@@ -337,8 +338,11 @@ __device__ __forceinline__ void fill_hole(int W, int H, int t, int x, int y, con
 // Hole fill, then discontinuity rejection (8-neighbourhood of the filled
 // map, decided before any rejection) and the search limits d^ +- k sigma,
 // rounded outward.  A block fills a 64 x 4 tile plus a one-pixel halo in
-// LDS, so the filled map never goes to memory.
+// LDS, so the filled map never goes to memory; the splat results it reads
+// (the tile plus a two-pixel margin) are staged in LDS first, all loads at once.
 constexpr int FD_TW = 64, FD_TH = 4, FD_LW = FD_TW + 2, FD_LN = FD_LW * (FD_TH + 2);
+constexpr int FD_SW = FD_TW + 4, FD_SN = FD_SW * (FD_TH + 4);
+constexpr int FD_SPER = (FD_SN + FD_TW * FD_TH - 1) / (FD_TW * FD_TH);   // staged entries per thread
 
 __global__ __launch_bounds__(FD_TW *FD_TH) void k_fill_disc(int W, int H, int D, CorrectConst cc,
                                                             const uint8_t *__restrict__ has,
@@ -350,14 +354,46 @@ __global__ __launch_bounds__(FD_TW *FD_TH) void k_fill_disc(int W, int H, int D,
 {
     __shared__ double sd[FD_LN], sp[FD_LN];
     __shared__ uint8_t spr[FD_LN], srs[FD_LN];
+    __shared__ double gdw[FD_SN], gpw[FD_SN];
+    __shared__ uint8_t ghas[FD_SN], grw[FD_SN];
     const int x0 = blockIdx.x * FD_TW - 1, y0 = blockIdx.y * FD_TH - 1;
+    {
+        // stage the splat results of pixels (x0 - 1 .., y0 - 1 ..); outside the image: none
+        double vd[FD_SPER], vp[FD_SPER];
+        uint8_t vh[FD_SPER], vr[FD_SPER];
+#pragma unroll
+        for (int k = 0; k < FD_SPER; k++) {
+            const int i = threadIdx.x + k * FD_TW * FD_TH;
+            const int sy = i / FD_SW, sx = i - sy * FD_SW;
+            const int x = x0 - 1 + sx, y = y0 - 1 + sy;
+            const bool in = i < FD_SN && x >= 0 && x < W && y >= 0 && y < H;
+            const int t = in ? y * W + x : 0;
+            vh[k] = has[t];
+            vr[k] = rw[t];
+            vd[k] = dw[t];
+            vp[k] = pw[t];
+            if (!in)
+                vh[k] = vr[k] = 0;
+        }
+#pragma unroll
+        for (int k = 0; k < FD_SPER; k++) {
+            const int i = threadIdx.x + k * FD_TW * FD_TH;
+            if (i < FD_SN) {
+                ghas[i] = vh[k];
+                grw[i] = vr[k];
+                gdw[i] = vd[k];
+                gpw[i] = vp[k];
+            }
+        }
+    }
+    __syncthreads();
     for (int i = threadIdx.x; i < FD_LN; i += FD_TW * FD_TH) {
         const int ly = i / FD_LW, lx = i - ly * FD_LW;
         const int x = x0 + lx, y = y0 + ly;
         uint8_t pr = 0, rv = 0;
         double dv = 0.0, pv = 0.0;
         if (x >= 0 && x < W && y >= 0 && y < H)
-            fill_hole(W, H, y * W + x, x, y, has, dw, pw, rw, pr, dv, pv, rv);
+            fill_hole(W, H, (ly + 1) * FD_SW + lx + 1, FD_SW, x, y, ghas, gdw, gpw, grw, pr, dv, pv, rv);
         spr[i] = pr;   // outside the image: no prediction (no neighbour)
         sd[i] = dv;
         sp[i] = pv;
