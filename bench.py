@@ -39,10 +39,21 @@ METRIC = "frames/s and cost-cells/s, reduced vs full SGM at 1242×375×128, 1 GP
 AGG_BYTES_PER_PIXEL_PATH = 22
 AGG_BYTES_PER_CELL_PATH = 1
 WTA_BYTES_PER_PIXEL = 53
+# The survey's per-cell model for aggregation with the cost computed on the
+# fly from census strings (the schedule built): 28 B per cell for all eight
+# paths (a 16-bit sum written once, read-modify-written by six more paths and
+# read by the winner search), i.e. 3.5 B per cell per path.  `achieved` uses
+# this model; the model above (what this implementation's kernels must move)
+# is reported beside it.
+SURVEY_BYTES_PER_CELL_PATH = 28.0 / 8.0
+# VALU issue capacity: 256 CUs x 4 SIMDs, one wave64 VALU instruction per
+# SIMD every 4 cycles at 2.4 GHz
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 KERNEL_NAMES = {"agg_h": "k_agg_h2 speculative + fix-up + cleanup launches (Eq. 1, horizontal paths)",
                 "agg_v": "k_agg_v2 (Eq. 1, vertical + diagonal paths, ragged windows)",
                 "wta": "k_wta_correct (WTA, sub-pixel, Kalman, chi2)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{kernel}_driving.txt")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_{kernel}_driving.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1809_07986_amd", "csrc", "sgm_kernels.hip")
 
 
@@ -70,10 +81,9 @@ def source_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def read_traffic(kernel: str):
-    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source (else None)."""
-    path = TRAFFIC_FILE.format(kernel=kernel)
+def _read_kv(path: str):
+    """key = value lines of a committed counter summary, or None if it is
+    missing or was taken on another kernel source."""
     if not os.path.exists(path):
         return None
     kv = {}
@@ -83,8 +93,25 @@ def read_traffic(kernel: str):
             kv[k.strip()] = v.strip()
     if kv.get("source_sha") != source_sha():
         return None
+    return kv
+
+
+def read_traffic(kernel: str):
+    """Per-launch HBM bytes of `kernel` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source (else None)."""
+    kv = _read_kv(TRAFFIC_FILE.format(kernel=kernel))
     try:
-        return float(kv["bytes_per_launch"])
+        return float(kv["bytes_per_launch"]) if kv else None
+    except (KeyError, ValueError):
+        return None
+
+
+def read_valu(kernel: str):
+    """Wave VALU instructions per launch of `kernel` (SQ_INSTS_VALU) from the
+    committed counter summary taken on the current kernel source, else None."""
+    kv = _read_kv(VALU_FILE.format(kernel=kernel))
+    try:
+        return float(kv["valu_insts_per_launch"]) if kv else None
     except (KeyError, ValueError):
         return None
 
@@ -99,7 +126,7 @@ def algorithmic_bytes(stage: str, n_px: int, cells: float, npaths_h: int = 2, np
     return None
 
 
-def cpu_baseline(seq, frames: int):
+def _oracle_frames(seq, frames: int):
     import oracle as O
     prm = O.Params(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
     F = O.OracleFilter(prm)
@@ -109,12 +136,69 @@ def cpu_baseline(seq, frames: int):
     for k in range(1, frames + 1):
         F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
         cells += int((F.hi - F.lo + 1).sum())
-    dt = time.perf_counter() - t0
-    return {"value": frames / dt, "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"driving 1242x375x128, reduced frames 1-{frames} after an untimed full frame 0 "
-                      f"(single-threaded C oracle, {cells / frames / 1e6:.2f} M cells/frame, "
-                      f"{cells / dt / 1e6:.1f} M cells/s)",
-            "seconds": dt}
+    return time.perf_counter() - t0, cells
+
+
+def roofline_entry(dom: str, dom_ms: float, n_px: int, mean_cells: float):
+    """Roofline object of the dominant kernel: algorithmic bytes per launch
+    (the survey's per-cell model for the aggregation kernels, the kernel's
+    own byte model otherwise) over its average HIP-event launch time, the
+    builder's byte model beside it, the measured HBM traffic and VALU issue
+    when counters taken on the current source are committed."""
+    paths = {"agg_v": 6, "agg_h": 2}.get(dom)
+    own_bytes = algorithmic_bytes(dom, n_px, mean_cells)
+    alg_bytes = SURVEY_BYTES_PER_CELL_PATH * paths * mean_cells if paths else own_bytes
+    achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
+    traffic = read_traffic(dom)
+    ent = {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
+           "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "algorithmic_bytes_per_launch": int(alg_bytes),
+           "byte_model": ("28 B/cell for 8 paths (cost on the fly), x %d/8 paths" % paths) if paths
+           else "kernel's own model",
+           "avg_launch_ms": round(dom_ms, 5),
+           "own_model_bytes_per_launch": int(own_bytes),
+           "own_model_gbs": round(own_bytes / (dom_ms * 1e-3) / 1e9, 1)}
+    if traffic:
+        ent["traffic_over_own_model"] = round(traffic / own_bytes, 3)
+    valu = read_valu(dom)
+    if valu:
+        ent["valu"] = {"wave_insts_per_launch": valu,
+                       "issue_frac": round(valu / (dom_ms * 1e-3) / VALU_WAVE_INSTR_PER_S, 4),
+                       "lane_ops_per_path_cell": round(valu * 64 / (mean_cells * paths), 1) if paths else None}
+    return ent
+
+
+def cpu_baseline(seq, frames: int, frames_1t: int):
+    """The oracle (plain C, double precision) on the host cores: the OpenMP
+    build of the same source on every thread it gets (identical results to
+    the one-thread build), and the one-thread parity build for reference."""
+    import oracle as O
+    threads = O.use_threads(True)
+    try:
+        dt, cells = _oracle_frames(seq, frames)
+    finally:
+        O.use_threads(False)
+    out = {"value": frames / dt, "unit": "frames/s", "cores": threads, "kind": "oracle",
+           "sample": f"driving 1242x375x128, reduced frames 1-{frames} after an untimed full frame 0 "
+                     f"(C oracle built with OpenMP, {threads} threads, {cells / frames / 1e6:.2f} M cells/frame, "
+                     f"{cells / dt / 1e6:.1f} M cells/s)",
+           "seconds": dt, "host_cpu": _host_cpu()}
+    if frames_1t > 0:
+        dt1, _ = _oracle_frames(seq, frames_1t)
+        out["one_thread"] = {"value": frames_1t / dt1, "unit": "frames/s", "cores": 1,
+                             "sample": f"reduced frames 1-{frames_1t}, one-thread parity build", "seconds": dt1}
+    return out
+
+
+def _host_cpu():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def main():
@@ -123,7 +207,8 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--full-steps", type=int, default=100)
-    ap.add_argument("--cpu-frames", type=int, default=12)
+    ap.add_argument("--cpu-frames", type=int, default=19)
+    ap.add_argument("--cpu-frames-1t", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-full", action="store_true", help="skip the full-range comparison (profiling runs)")
     ap.add_argument("--workload", choices=("driving", "batched", "learned"), default="driving",
@@ -265,13 +350,8 @@ def main():
     # diagonal kernel or the WTA kernel, whichever is longer
     kern = {k: v for k, v in stage_avg.items() if k in ("agg_v", "wta")}
     dom = max(kern, key=kern.get)
-    dom_bytes = algorithmic_bytes(dom, H * W, mean_cells)
     dom_ms = kern[dom]
-    achieved = dom_bytes / (dom_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom],
-                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(dom),
-                "algorithmic_bytes_per_launch": int(dom_bytes), "avg_launch_ms": round(dom_ms, 5)}
+    roofline = roofline_entry(dom, dom_ms, H * W, mean_cells)
 
     out = {
         "metric": METRIC,
@@ -305,7 +385,7 @@ def main():
     if not args.no_learned:
         out["learned_window"] = bench_learned(args)
     if not args.no_cpu:
-        cb = cpu_baseline(seq, args.cpu_frames)
+        cb = cpu_baseline(seq, args.cpu_frames, args.cpu_frames_1t)
         out["cpu_baseline"] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in cb.items()}
     print(json.dumps(out), flush=True)
 

@@ -58,7 +58,8 @@ extern "C" {
 typedef struct sgm_context sgm_context;
 
 typedef struct {
-    int32_t width, height;      /* 16 <= width <= 4096, 16 <= height, width*height <= 2^24 */
+    int32_t width, height;      /* 16 <= width <= 4096, 16 <= height, width*height <= 2^24,
+                                   width*height*max_disp < 2^32 */
     int32_t max_disp;           /* disparities 0..max_disp-1, 2 <= max_disp <= 256 */
     int32_t census_w, census_h; /* odd census window, census_w*census_h-1 <= 64 bits */
     uint32_t path_mask;         /* bit k enables path k: 0 (+1,0) 1 (-1,0) 2 (0,+1) 3 (0,-1)
@@ -126,13 +127,20 @@ int sgm_get_motion_mask(sgm_context *ctx, uint8_t *out, int32_t out_pitch, void 
 int sgm_get_disparity_median(sgm_context *ctx, float *out, int32_t out_pitch, void *stream);
 
 /* Filter state (checkpoint / restore): d, p as float64 and the per-pixel
- * RESET flags, dense width*height arrays. */
+ * RESET flags, dense width*height arrays.  (float64 rather than float32: the
+ * library keeps the whole filter in double precision.)
+ * sgm_set_state checks the state first and synchronises the stream to read
+ * the result: SGM_EINVAL, with the context unchanged, if any pixel has a
+ * non-finite d or p, d outside [0, max_disp-1] or p <= 0 (states the filter
+ * cannot reach; every state sgm_get_state returns passes).  -0.0 is stored
+ * as +0.0.  It also clears the carried innovation (learned windows). */
 int sgm_get_state(sgm_context *ctx, double *d, double *p, uint8_t *sflags, void *stream);
 int sgm_set_state(sgm_context *ctx, const double *d, const double *p, const uint8_t *sflags,
                   void *stream);
 
-/* The matcher alone on caller-given windows (Section 2: "SGM also inputs
- * two values for each pixel that define the range for disparity search"):
+/* The matcher alone on caller-given windows (Section 2: besides the image
+ * pair, the matcher is given a lower and an upper disparity bound for every
+ * pixel and searches only between them):
  * lo, hi int32 per pixel, 0 <= lo <= hi < max_disp (checked on the device;
  * violations are clamped and reported by sgm_get_stage SGM_STAGE_STATUS).
  * Writes the integer winner d* (int32) and the sub-pixel measurement d_z

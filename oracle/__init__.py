@@ -20,7 +20,7 @@ from typing import Optional
 
 import numpy as np
 
-__all__ = ["Params", "build", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux", "median3x3",
+__all__ = ["Params", "build", "use_threads", "census", "cost", "aggregate", "wta", "match", "predict", "predict_aux", "median3x3",
            "DetectParams", "motion_values", "integral", "detect_windows", "merge_boxes", "detect",
            "learned_windows", "correct", "correct_ex", "OracleFilter", "PRED", "RESET", "FULLWIN", "GATEFAIL",
            "PATH_DX", "PATH_DY"]
@@ -33,19 +33,37 @@ PATH_DY = (0, 0, +1, -1, +1, -1, +1, -1)
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "sgm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source with -fopenmp: its parallel loops on several threads, same results (CPU baseline)
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 _lock = threading.Lock()
-_lib = None
+_libs = {}
+_threaded = False
+
+
+def _build_one(lib: str, extra, force: bool):
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(_SRC):
+        return lib
+    tmp = lib + f".tmp{os.getpid()}"
+    subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-Wno-unknown-pragmas", "-ffp-contract=off",
+                    "-fno-fast-math", "-shared", "-fPIC"] + extra + [_SRC, "-o", tmp, "-lm"], check=True)
+    os.replace(tmp, lib)
+    return lib
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no FMA contraction) into oracle/liboracle.so."""
-    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
-        return _LIB
-    tmp = _LIB + f".tmp{os.getpid()}"
-    subprocess.run(["gcc", "-O2", "-std=c99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
-                    "-shared", "-fPIC", _SRC, "-o", tmp, "-lm"], check=True)
-    os.replace(tmp, _LIB)
-    return _LIB
+    """Compile the oracle with gcc (no FMA contraction): oracle/liboracle.so
+    (one thread, the parity reference) and oracle/liboracle_omp.so (-fopenmp)."""
+    _build_one(_LIB_OMP, ["-fopenmp"], force)
+    return _build_one(_LIB, [], force)
+
+
+def use_threads(on: bool) -> int:
+    """Route every oracle call through the OpenMP build (True) or the
+    one-thread build (False, the default).  Returns the thread count the
+    selected build uses."""
+    global _threaded
+    _threaded = bool(on)
+    return int(_load().orc_threads())
 
 
 class _CParams(ctypes.Structure):
@@ -96,11 +114,11 @@ class Params:
 
 
 def _load():
-    global _lib
     with _lock:
-        if _lib is None:
+        key = "omp" if _threaded else "1t"
+        if key not in _libs:
             build(force=False)
-            lib = ctypes.CDLL(_LIB)
+            lib = ctypes.CDLL(_LIB_OMP if _threaded else _LIB)
             P = ctypes.c_void_p
             i = ctypes.c_int
             lib.orc_census.argtypes = [P, i, i, i, i, P]
@@ -124,10 +142,11 @@ def _load():
             for name in ("orc_census", "orc_cost", "orc_aggregate", "orc_wta", "orc_match", "orc_predict",
                          "orc_correct", "orc_full_frame", "orc_reduced_frame", "orc_predict_aux",
                          "orc_learned_windows", "orc_correct_ex", "orc_median3x3", "orc_motion_values",
-                         "orc_integral", "orc_detect_windows", "orc_merge_boxes", "orc_detect"):
+                         "orc_integral", "orc_detect_windows", "orc_merge_boxes", "orc_detect", "orc_threads"):
                 getattr(lib, name).restype = ctypes.c_int
-            _lib = lib
-    return _lib
+            lib.orc_threads.argtypes = []
+            _libs[key] = lib
+        return _libs[key]
 
 
 def _p(a: Optional[np.ndarray]):

@@ -9,13 +9,17 @@
  * check and the benchmark's CPU baseline.
  *
  * Dense storage, scalar loops, double precision for every floating-point
- * quantity, one thread.  Each function names the passage of the paper it
- * follows.  Where the paper is silent the reading used is stated at the
- * function (the design notes list all of them).
+ * quantity.  Each function names the passage of the paper it follows.  Where
+ * the paper is silent the reading used is stated at the function (the design
+ * notes list all of them).
  *
  * Build: gcc -O2 -std=c99 -ffp-contract=off -shared -fPIC (no FMA
  * contraction, so every floating-point operation is one IEEE-754 rounding in
- * the order written).
+ * the order written).  That build runs on one thread and is the parity
+ * reference.  The same source built with -fopenmp (the CPU baseline) runs the
+ * loops marked "omp" on several threads: each such loop's iterations write
+ * disjoint outputs and read only values finished before the loop, so both
+ * builds give identical results.
  */
 #include "sgm_oracle.h"
 
@@ -42,6 +46,7 @@ int orc_census(const uint8_t *img, int W, int H, int cw, int ch, uint64_t *out)
     if (cw < 1 || ch < 1 || (cw % 2) == 0 || (ch % 2) == 0 || cw * ch - 1 > 64)
         return -1;
     int rx = cw / 2, ry = ch / 2;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
             uint8_t c = img[y * W + x];
@@ -82,6 +87,7 @@ static int popcount64(uint64_t v)
 int orc_cost(const uint64_t *cl, const uint64_t *cr, int W, int H, int D, int nbits,
              const int32_t *lo, const int32_t *hi, int32_t *C)
 {
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
             int p = y * W + x;
@@ -120,7 +126,42 @@ static const int PATH_DY[8] = {0, 0, +1, -1, +1, -1, +1, -1};
  * outside the image starts the path: L_r(p,d) = C(p,d).
  * The sum over the selected paths is S(p,d) = sum_r L_r(p,d), for d in W_p.
  * If Lr_out is not NULL, path k's L_r is stored at Lr_out[k][p][d].
+ *
+ * Visit order: the predecessor p - r is always finished before p.  A
+ * horizontal path's scanlines are the image rows, independent of each other
+ * (omp: rows in parallel); for the other paths p - r lies in the previous row
+ * of the sweep, so the pixels of one row are independent (omp: the pixels of
+ * a row in parallel, rows in sweep order).
  * ---------------------------------------------------------------------- */
+
+/* Eq. (1) at pixel (x, y) of path (rx, ry), from its finished predecessor */
+static void agg_pixel(const int32_t *C, int32_t *Lr, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+                      int p1, int p2, int rx, int ry, int x, int y)
+{
+    int p = y * W + x;
+    int qx = x - rx, qy = y - ry;
+    if (qx < 0 || qx >= W || qy < 0 || qy >= H) {
+        for (int d = lo[p]; d <= hi[p]; d++)
+            Lr[(size_t)p * D + d] = C[(size_t)p * D + d];
+        return;
+    }
+    int q = qy * W + qx;
+    int mq = ORC_INF;
+    for (int i = lo[q]; i <= hi[q]; i++)
+        if (Lr[(size_t)q * D + i] < mq)
+            mq = Lr[(size_t)q * D + i];
+    for (int d = lo[p]; d <= hi[p]; d++) {
+        int best = mq + p2;
+        if (d >= lo[q] && d <= hi[q] && Lr[(size_t)q * D + d] < best)
+            best = Lr[(size_t)q * D + d];
+        if (d - 1 >= lo[q] && d - 1 <= hi[q] && Lr[(size_t)q * D + d - 1] + p1 < best)
+            best = Lr[(size_t)q * D + d - 1] + p1;
+        if (d + 1 >= lo[q] && d + 1 <= hi[q] && Lr[(size_t)q * D + d + 1] + p1 < best)
+            best = Lr[(size_t)q * D + d + 1] + p1;
+        Lr[(size_t)p * D + d] = C[(size_t)p * D + d] + best - mq;
+    }
+}
+
 int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, const int32_t *hi,
                   int p1, int p2, unsigned path_mask, int32_t *S, int32_t *Lr_out)
 {
@@ -128,6 +169,7 @@ int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, cons
     int32_t *Lr = (int32_t *)malloc(cells * sizeof(int32_t));
     if (!Lr)
         return -2;
+#pragma omp parallel for schedule(static)
     for (int y = 0; y < H; y++)
         for (int x = 0; x < W; x++) {
             int p = y * W + x;
@@ -138,35 +180,20 @@ int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, cons
         if (!(path_mask & (1u << k)))
             continue;
         int rx = PATH_DX[k], ry = PATH_DY[k];
-        /* visit order: the predecessor p - r is always visited before p */
-        for (int iy = 0; iy < H; iy++) {
-            int y = (ry >= 0) ? iy : H - 1 - iy;
-            for (int ix = 0; ix < W; ix++) {
-                int x = (rx >= 0) ? ix : W - 1 - ix;
-                int p = y * W + x;
-                int qx = x - rx, qy = y - ry;
-                if (qx < 0 || qx >= W || qy < 0 || qy >= H) {
-                    for (int d = lo[p]; d <= hi[p]; d++)
-                        Lr[(size_t)p * D + d] = C[(size_t)p * D + d];
-                    continue;
-                }
-                int q = qy * W + qx;
-                int mq = ORC_INF;
-                for (int i = lo[q]; i <= hi[q]; i++)
-                    if (Lr[(size_t)q * D + i] < mq)
-                        mq = Lr[(size_t)q * D + i];
-                for (int d = lo[p]; d <= hi[p]; d++) {
-                    int best = mq + p2;
-                    if (d >= lo[q] && d <= hi[q] && Lr[(size_t)q * D + d] < best)
-                        best = Lr[(size_t)q * D + d];
-                    if (d - 1 >= lo[q] && d - 1 <= hi[q] && Lr[(size_t)q * D + d - 1] + p1 < best)
-                        best = Lr[(size_t)q * D + d - 1] + p1;
-                    if (d + 1 >= lo[q] && d + 1 <= hi[q] && Lr[(size_t)q * D + d + 1] + p1 < best)
-                        best = Lr[(size_t)q * D + d + 1] + p1;
-                    Lr[(size_t)p * D + d] = C[(size_t)p * D + d] + best - mq;
-                }
+        if (ry == 0) {
+#pragma omp parallel for schedule(static)
+            for (int y = 0; y < H; y++)
+                for (int ix = 0; ix < W; ix++)
+                    agg_pixel(C, Lr, W, H, D, lo, hi, p1, p2, rx, ry, (rx >= 0) ? ix : W - 1 - ix, y);
+        } else {
+            for (int iy = 0; iy < H; iy++) {
+                int y = (ry >= 0) ? iy : H - 1 - iy;
+#pragma omp parallel for schedule(static)
+                for (int x = 0; x < W; x++)
+                    agg_pixel(C, Lr, W, H, D, lo, hi, p1, p2, rx, ry, x, y);
             }
         }
+#pragma omp parallel for schedule(static)
         for (int y = 0; y < H; y++)
             for (int x = 0; x < W; x++) {
                 int p = y * W + x;
@@ -192,6 +219,7 @@ int orc_aggregate(const int32_t *C, int W, int H, int D, const int32_t *lo, cons
 int orc_wta(const int32_t *S, int W, int H, int D, const int32_t *lo, const int32_t *hi,
             int32_t *dstar, double *dz)
 {
+#pragma omp parallel for schedule(static)
     for (int p = 0; p < W * H; p++) {
         const int32_t *s = S + (size_t)p * D;
         int best = lo[p];
@@ -480,6 +508,7 @@ int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, 
                    const double *rpix, double *d, double *p, uint8_t *mask, uint8_t *sflags, double *nu_out)
 {
     int n = prm->width * prm->height, D = prm->max_disp;
+#pragma omp parallel for schedule(static)
     for (int t = 0; t < n; t++) {
         double r = rpix ? rpix[t] : prm->r;
         int moving = 0;
@@ -761,3 +790,12 @@ int orc_detect(const orc_detect_params *dp, const double *dhat, const double *dz
     free(S);
     return n;
 }
+
+/* Threads the parallel loops use: omp_get_max_threads() in the -fopenmp
+ * build, 1 in the parity build. */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_threads(void) { return 1; }
+#endif

@@ -69,6 +69,10 @@ int validate(const sgm_params *p)
                     p->height);
     if (p->max_disp < 2 || p->max_disp > kMaxDisp)
         return fail(SGM_EINVAL, "max_disp %d outside [2, %d]", p->max_disp, kMaxDisp);
+    // ragged offsets and cell counts are 32-bit
+    if ((int64_t)p->width * p->height * p->max_disp > (int64_t)UINT32_MAX)
+        return fail(SGM_EINVAL, "width*height*max_disp = %lld cells exceeds 2^32 - 1",
+                    (long long)p->width * p->height * p->max_disp);
     if (p->census_w < 1 || p->census_h < 1 || !(p->census_w & 1) || !(p->census_h & 1) || p->census_w > 15 ||
         p->census_h > 15 || p->census_w * p->census_h - 1 > 64)
         return fail(SGM_EINVAL, "census window %dx%d must be odd, <= 15 and hold <= 64 bits", p->census_w,
@@ -726,15 +730,20 @@ int sgm_set_state(sgm_context *ctx, const double *d, const double *p, const uint
         return rc;
     if (!d || !p || !sflags)
         return fail(SGM_EINVAL, "state pointer is NULL");
-    const size_t N = ctx->g.N;
     hipStream_t s = as_stream(stream);
-    hipError_t e = hipMemcpyAsync(ctx->b.d, d, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+    // validate before touching the context: a rejected state leaves it as it was
+    uint32_t bad = 0;
+    hipError_t e = launch_check_state(ctx->g, d, p, ctx->b.status + 1, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->b.p, p, N * sizeof(double), hipMemcpyDeviceToDevice, s);
+        e = hipMemcpyAsync(&bad, ctx->b.status + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->b.sflags, sflags, N, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(ctx->b.nu, 0, N * sizeof(double), s);
+        e = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "state check");
+    if (bad)
+        return fail(SGM_EINVAL, "%u pixels of the state have d outside [0, %d], a non-finite d or p, or p <= 0",
+                    bad, ctx->g.D - 1);
+    e = launch_load_state(ctx->g, ctx->b, d, p, sflags, s);
     if (e != hipSuccess)
         return hip_fail(e, "state copy");
     ctx->started = true;

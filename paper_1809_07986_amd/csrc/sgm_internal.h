@@ -122,6 +122,10 @@ hipError_t launch_windows_to_lohi(const Geometry &g, const DevBuffers &b, int32_
                                   hipStream_t s);
 hipError_t launch_state_to_f32(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);
 hipError_t launch_copy_u8(const Geometry &g, const uint8_t *src, uint8_t *dst, int pitch, hipStream_t s);
+// injected state: count invalid entries into *bad (zeroed first); copy into the context
+hipError_t launch_check_state(const Geometry &g, const double *d, const double *p, uint32_t *bad, hipStream_t s);
+hipError_t launch_load_state(const Geometry &g, DevBuffers &b, const double *d, const double *p, const uint8_t *sf,
+                             hipStream_t s);
 hipError_t launch_median3x3(const Geometry &g, const double *src, float *dst, int pitch, hipStream_t s);
 
 // moving-object detection: window grid and grouping settings (kernel argument)

@@ -1901,6 +1901,55 @@ hipError_t launch_copy_u8(const Geometry &g, const uint8_t *src, uint8_t *dst, i
 }
 
 // ---------------------------------------------------------------------------
+// injected filter state (checkpoint restore): the state must be one the
+// filter can hold, d in [0, D-1] and p > 0, both finite.  The check counts
+// the pixels that break it; the copy stores -0 as +0, so that the z-buffer's
+// ordering of disparities by their bits agrees with their values.
+// ---------------------------------------------------------------------------
+__global__ void k_check_state(int N, int D, const double *__restrict__ d, const double *__restrict__ p,
+                              uint32_t *bad)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    bool ok = true;
+    if (t < N) {
+        const double dv = d[t], pv = p[t];
+        ok = isfinite(dv) && dv >= 0.0 && dv <= (double)(D - 1) && isfinite(pv) && pv > 0.0;
+    }
+    const unsigned long long m = __ballot(!ok);
+    if (m && (threadIdx.x & 63) == 0)
+        atomicAdd(bad, (uint32_t)__popcll(m));
+}
+
+__global__ void k_load_state(int N, const double *__restrict__ d, const double *__restrict__ p,
+                             const uint8_t *__restrict__ sf, double *__restrict__ sd, double *__restrict__ sp,
+                             uint8_t *__restrict__ ssf, double *__restrict__ nu)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= N)
+        return;
+    const double dv = d[t];
+    sd[t] = dv == 0.0 ? 0.0 : dv;
+    sp[t] = p[t];
+    ssf[t] = sf[t];
+    nu[t] = 0.0;
+}
+
+hipError_t launch_check_state(const Geometry &g, const double *d, const double *p, uint32_t *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, bad);
+    hipLaunchKernelGGL(k_check_state, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.D, d, p, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_state(const Geometry &g, DevBuffers &b, const double *d, const double *p, const uint8_t *sf,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_load_state, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, d, p, sf, b.d, b.p, b.sflags,
+                       b.nu);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // 3x3 block median of the filtered disparity (Section 2.3 post-processing,
 // outside the filter loop), clamped borders, written as float32.  The median
 // of 3x3 values: sort each row of three, then the median is the median of

@@ -157,10 +157,11 @@ def _hit_plane(pl: _Plane, o: np.ndarray, dw: np.ndarray):
     with np.errstate(divide="ignore", invalid="ignore"):
         t = (pl.h - o @ pl.n) / denom
     t = np.where(np.abs(denom) > 1e-12, t, np.inf)
-    P = o[None, :] + t[:, None] * dw
+    # rays parallel to the plane (t = inf) take t = 0 here; they are rejected below
+    P = o[None, :] + np.where(np.isfinite(t), t, 0.0)[:, None] * dw
     u = P @ pl.u_axis
     v = P @ pl.v_axis
-    ok = t > 0.05
+    ok = (t > 0.05) & np.isfinite(t)
     if pl.bounds is not None:
         ok &= (u >= pl.bounds[0]) & (u <= pl.bounds[1]) & (v >= pl.bounds[2]) & (v <= pl.bounds[3])
     t = np.where(ok, t, np.inf)

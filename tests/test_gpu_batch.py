@@ -12,7 +12,12 @@ torch = pytest.importorskip("torch")
 if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
+import oracle as O  # noqa: E402
 import paper_1809_07986_amd as sgmk  # noqa: E402
+from paper_1809_07986_amd import _native as NAT  # noqa: E402
+
+D_TOL = 1e-4
+P_TOL = 1e-4
 
 
 def _say(msg):
@@ -74,6 +79,40 @@ def test_batch_matches_independent_contexts():
             for x, y in zip(a, s):
                 assert np.array_equal(x, y), (k, i)
         _say(f"step {k}: identical")
+
+
+def test_batch_streams_match_oracle():
+    # every stream of an uneven batch against its own oracle filter, frame by
+    # frame: state, mask, windows, winners and measurements (Section 2.4,
+    # Eq. 2-6 per stream; the batch only changes where the work runs)
+    seqs = _sequences()
+    _say("case: batch of 4 uneven streams vs the oracle")
+    b = _batch(seqs)
+    oracles = []
+    for st, q in zip(STREAMS, seqs):
+        F = O.OracleFilter(O.Params(st["width"], st["height"], st["max_disp"], f=st["f"], baseline=0.54))
+        F.full_frame(q.left[0], q.right[0])
+        oracles.append(F)
+    for k in (1, 2):
+        Ts = [q.T[k] for q in seqs]
+        for i, q in enumerate(seqs):
+            b.load(i, q.left[k], q.right[k])
+        b.step(np.stack(Ts))
+        for F, q, T in zip(oracles, seqs, Ts):
+            F.reduced_frame(q.left[k], q.right[k], T)
+        torch.cuda.synchronize()
+        for i, (c, F) in enumerate(zip(b.contexts, oracles)):
+            d, p, sf = (t.cpu().numpy() for t in c.get_state())
+            assert np.max(np.abs(d - F.d)) <= D_TOL, (k, i)
+            assert np.max(np.abs(p - F.p) / np.maximum(F.p, 1e-12)) <= P_TOL, (k, i)
+            assert np.array_equal(sf, F.sflags), (k, i)
+            assert np.array_equal(c.motion_mask().cpu().numpy(), F.mask), (k, i)
+            assert np.array_equal(c.stage(NAT.STAGE_LO).cpu().numpy(), F.lo), (k, i)
+            assert np.array_equal(c.stage(NAT.STAGE_HI).cpu().numpy(), F.hi), (k, i)
+            assert np.array_equal(c.stage(NAT.STAGE_DSTAR).cpu().numpy(), F.dstar), (k, i)
+            assert np.array_equal(c.stage(NAT.STAGE_FLAGS).cpu().numpy(), F.flags), (k, i)
+            assert np.max(np.abs(c.stage(NAT.STAGE_DZ).cpu().numpy() - F.dz)) <= D_TOL, (k, i)
+        _say(f"step {k}: every stream matches its oracle")
 
 
 @pytest.mark.skip(reason="captured-graph stepping is disabled in the library: its first run crashed the host "

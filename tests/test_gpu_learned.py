@@ -9,7 +9,9 @@ Tolerances:
     precision operations);
   * network output against the fp64 oracle: relative L2 error <= 2e-2 per
     channel (bfloat16 weights and activations, fp32 accumulation; each layer
-    rounds its output to 8 significant bits);
+    rounds its output to 8 significant bits), and element by element within
+    a bound propagated through the network from those roundings
+    (_elementwise_bound);
   * parameter gradients: relative L2 error <= 5e-2 per layer tensor
     (bfloat16 activations and activation gradients);
   * head (exp in fp32): 1e-6 relative; loss: 1e-5 relative; Adam: 1e-6.
@@ -74,6 +76,47 @@ def _bf16_input(rng, shape):
     return bits, cnn.bf16_value(bits)
 
 
+def _elementwise_bound(theta_ref, x):
+    """Per-element bound on |GPU output - fp64 output| for input x (exact
+    bfloat16 values) and parameters theta_ref (bfloat16 weights as the GPU
+    applies them).
+
+    Layer l of the GPU computes z_G = W a_G + b with fp32 accumulation of
+    K = 9 ci + 1 terms (products of two bfloat16 values are exact in fp32),
+    then a_G = bf16(relu(z_G)) (layers 1-4) or o = z_G (layer 5, fp32).  The
+    oracle computes z = W a + b and a = relu(z) exactly.  With e the bound on
+    |a_G - a| of the layer input:
+        |z_G - z| <= |W| * e + g_K (|W| * (|a| + e) + |b|),  g_K = 2 K 2^-24
+    (sequential fp32 summation bound, doubled for the matrix core's order),
+    and relu is 1-Lipschitz while rounding to bfloat16 moves a value by at
+    most 2^-8 of its magnitude, so the output bound of layers 1-4 is
+        e' = dz + 2^-8 (relu(z) + dz).
+    """
+    params = cnn.unpack(theta_ref)
+    a = np.asarray(x, np.float64)
+    e = np.zeros_like(a)
+    for li, (W, b) in enumerate(params):
+        K = 9 * W.shape[3] + 1
+        z = cnn.conv3x3(a, W, b)
+        aw = np.abs(W)
+        dz = cnn.conv3x3(e, aw) + 2.0 * K * 2.0 ** -24 * cnn.conv3x3(np.abs(a) + e, aw, np.abs(b))
+        if li < len(params) - 1:
+            a = np.maximum(z, 0.0)
+            e = dz + 2.0 ** -8 * (a + dz)
+        else:
+            a, e = z, dz
+    return a, e
+
+
+def _check_elementwise(out, theta_ref, x, label):
+    ref, bound = _elementwise_bound(theta_ref, x)
+    err = np.abs(np.asarray(out, np.float64) - ref)
+    ratio = float(np.max(err / np.maximum(bound, 1e-300)))
+    _say(f"  {label}: max |d| {err.max():.3e}, max |d| / bound {ratio:.3f}")
+    assert np.all(err <= bound), label
+    return ref
+
+
 # ---------------------------------------------------------------- network
 
 SHAPES = [(2, 37, 70), (1, 16, 32), (1, 9, 5)]
@@ -96,6 +139,24 @@ def test_cnn_forward_matches_oracle(n, h, w):
         _say(f"  channel {c}: rel L2 {err:.2e}")
         assert err <= 2e-2
     assert np.all(np.isfinite(out))
+    _check_elementwise(out, _gpu_reference_theta(theta), xv, f"{n}x{h}x{w}")
+
+
+def test_cnn_forward_full_size_elementwise():
+    # one 1242x375 image (the learned workload's frame size): every output
+    # element within the propagated rounding bound, with the shipped network
+    h, w = 375, 1242
+    _say(f"cnn forward 1x{h}x{w}, shipped network")
+    rng = np.random.default_rng(77)
+    theta = sgmk.load_window_model()
+    bits, xv = _bf16_input(rng, (1, h, w, 4))
+    tr = sgmk.CnnTrainer(1, h, w)
+    tr.set_params(theta)
+    out = _np(tr.forward(torch.from_numpy(bits.view(np.int16)).cuda()))
+    torch.cuda.synchronize()
+    ref = _check_elementwise(out, _gpu_reference_theta(theta), xv, "1242x375")
+    for c in range(2):
+        assert _rel_l2(out[..., c], ref[..., c]) <= 2e-2
 
 
 @pytest.mark.parametrize("n,h,w", SHAPES[:2])
@@ -242,6 +303,7 @@ def _learned_run(seq, theta, gate_rerun, frames=(1, 2), label=""):
         o_ref, _ = cnn.forward(th_ref, cnn.bf16_value(feat)[None])
         for c in range(2):
             assert _rel_l2(out[..., c], o_ref[0, ..., c]) <= 2e-2, (label, k, c)
+        _check_elementwise(out[None], th_ref, cnn.bf16_value(feat)[None], f"{label} frame {k}")
         hw = _np(g.stage(NAT.STAGE_HALFWIDTH)).astype(np.float64)
         rp = _np(g.stage(NAT.STAGE_RPIX)).astype(np.float64)
         hw_ref, rp_ref = cnn.head(out, o.prm.k_sigma)
@@ -270,6 +332,21 @@ def test_learned_frames_match_oracle(gate_rerun):
     stats = _learned_run(seq, _theta(3, o0_bias=0.5, o1_bias=-1.0), gate_rerun, label=f"rerun={gate_rerun}")
     if gate_rerun:
         assert any(s["gatefail"] > 0 for s in stats), "the moving box should fail the innovation test"
+
+
+def test_learned_frame_full_size_matches_oracle():
+    # the learned workload at full size (1242x375, D = 256) with the shipped
+    # network and the gate re-run: features, network output, windows, both
+    # matching passes and the filter state against the oracle
+    _say("learned frame, 1242x375x256, shipped network, gate re-run")
+    seq = synth.make_sequence("learned", frames=2, seed=4100)
+    O.use_threads(True)     # identical to the one-thread build (tests/test_oracle_threads.py)
+    try:
+        stats = _learned_run(seq, sgmk.load_window_model(), True, frames=(1,), label="learned full size")
+    finally:
+        O.use_threads(False)
+    n = seq.cam.width * seq.cam.height
+    assert 0 < stats[0]["full"] < n and stats[0]["cells"] < n * seq.max_disp
 
 
 def test_saturated_half_width_searches_the_full_range():

@@ -137,7 +137,8 @@ def test_shapes_paths_and_census(W, H, D, mask, cw, ch):
 @pytest.mark.parametrize("W,H,D", [(4096, 24, 128), (16, 2048, 100)])
 def test_largest_width_and_tall_images(W, H, D):
     # the widest image the library takes (most horizontal segments, longest
-    # diagonals) and a tall narrow one (the longest vertical chains)
+    # diagonals) and a tall narrow one (the longest vertical chains); every
+    # path's losses are compared
     _say(f"case: extreme shape {W}x{H}x{D}")
     rng = np.random.default_rng(W + H)
     left = rng.integers(0, 256, (H, W)).astype(np.uint8)
@@ -145,7 +146,31 @@ def test_largest_width_and_tall_images(W, H, D):
     g = sgmk.ReducedSGM(W, H, D, f=100.0)
     prm = O.Params(W, H, D, f=100.0)
     lo, hi = synth.random_windows(rng, H, W, D, max_width=12, full_frac=0.05)
-    _check_match(g, left, right, prm, lo, hi, f"extreme-{W}x{H}x{D}", paths=False)
+    _check_match(g, left, right, prm, lo, hi, f"extreme-{W}x{H}x{D}", paths=True)
+
+
+@pytest.mark.parametrize("W,H,full_frac,maxw", [(640, 48, 0.05, 12), (640, 48, 0.3, 40), (1920, 20, 0.04, 16)])
+def test_d256_images_much_wider_than_the_range(W, H, full_frac, maxw):
+    # D = 256 with W >> D: the kernels of the learned (1242x375x256) and the
+    # batched 1920x1080x256 workloads away from the x - d < 0 corner, with
+    # ragged and full-range windows and every path's losses compared
+    D = 256
+    _say(f"case: D=256 wide image {W}x{H}, full_frac={full_frac}")
+    rng = np.random.default_rng(W * 7 + H + int(full_frac * 100))
+    left = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    right = np.roll(left, -37, axis=1)
+    g = sgmk.ReducedSGM(W, H, D, f=0.58 * W)
+    prm = O.Params(W, H, D, f=0.58 * W)
+    lo, hi = synth.random_windows(rng, H, W, D, max_width=maxw, full_frac=full_frac, smooth=True)
+    O.use_threads(True)     # the OpenMP build: identical results (tests/test_oracle_threads.py)
+    try:
+        _check_match(g, left, right, prm, lo, hi, f"d256-{W}x{H}", paths=True)
+        if W == 640 and full_frac < 0.1:
+            lo = np.zeros((H, W), np.int32)
+            hi = np.full((H, W), D - 1, np.int32)
+            _check_match(g, left, right, prm, lo, hi, f"d256-full-{W}x{H}", paths=True)
+    finally:
+        O.use_threads(False)
 
 
 def test_pitched_images():
@@ -338,3 +363,82 @@ def test_driving_full_size_sequence():
     # frame and two reduced frames against the oracle, every pixel
     seq = synth.make_sequence("driving", frames=3)
     _run_sequence(seq, 3, "driving")
+
+
+def test_learned_workload_full_size_ksigma_frames():
+    # the learned workload's frames (1242x375, D = 256) with k-sigma windows:
+    # full frame and two reduced frames against the oracle, every pixel
+    seq = synth.make_sequence("learned", frames=3, seed=4100)
+    O.use_threads(True)     # identical to the one-thread build (tests/test_oracle_threads.py)
+    try:
+        g, F = _run_sequence(seq, 3, "learned 1242x375x256 k-sigma")
+    finally:
+        O.use_threads(False)
+    full = int(((F.flags & O.FULLWIN) != 0).sum())
+    _say(f"last frame: {g.cost_cells()} cells, {full} full-range pixels")
+    assert 0 < full < seq.cam.width * seq.cam.height
+
+
+def _corrupt_forward(T, dz):
+    E = np.eye(4)
+    E[2, 3] = dz
+    return E @ T
+
+
+def test_wrong_ego_motion_recovers_like_the_oracle():
+    # Section 2.4 / Section 4: a wrong ego-motion at frame 2 (1.5 m of extra
+    # forward motion) makes the prediction wrong; the innovation test and the
+    # window-edge rule reset those pixels, which search the full range in
+    # frame 3.  GPU and oracle agree on every frame, including the recovery.
+    seq = synth.make_sequence("tiny", frames=5)
+    H, W = seq.cam.height, seq.cam.width
+    g = sgmk.ReducedSGM(W, H, seq.max_disp, **_params(seq))
+    F = O.OracleFilter(_oracle_params(seq))
+    g.full_frame(seq.left[0], seq.right[0])
+    F.full_frame(seq.left[0], seq.right[0])
+    for k in range(1, 5):
+        T = _corrupt_forward(seq.T[k], -1.5) if k == 2 else seq.T[k]
+        _say(f"case: recovery frame {k}{' (wrong ego-motion)' if k == 2 else ''}")
+        g.reduced_frame(seq.left[k], seq.right[k], T)
+        F.reduced_frame(seq.left[k], seq.right[k], T)
+        torch.cuda.synchronize()
+        _compare_state(g, F, f"recovery frame {k}", True)
+        if k == 2:
+            pred = (F.flags & O.PRED) != 0
+            assert F.mask[pred].mean() > 0.2
+            assert (F.sflags & O.RESET).astype(bool).mean() > 0.1
+        if k == 3:
+            assert ((F.flags & O.FULLWIN) != 0).mean() > 0.3
+
+
+def test_set_state_rejects_unreachable_states():
+    seq = synth.make_sequence("tiny")
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    g = sgmk.ReducedSGM(W, H, D, **_params(seq))
+    g.full_frame(seq.left[0], seq.right[0])
+    torch.cuda.synchronize()
+    before = [_np(t) for t in g.get_state()]
+    d0, p0, f0 = before
+    for name, (i, j, dv, pv) in {"nan d": (3, 5, np.nan, 1.0), "negative d": (0, 0, -0.5, 1.0),
+                                "d above the range": (7, 9, D - 0.5, 1.0), "inf p": (2, 2, 3.0, np.inf),
+                                "zero p": (1, 1, 3.0, 0.0), "negative p": (4, 4, 3.0, -1.0)}.items():
+        d, p = d0.copy(), p0.copy()
+        d[i, j], p[i, j] = dv, pv
+        with pytest.raises(sgmk.SgmError) as e:
+            g.set_state(d, p, f0)
+        assert e.value.code == NAT.SGM_EINVAL, name
+        after = [_np(t) for t in g.get_state()]
+        for a, b in zip(before, after):
+            assert np.array_equal(a, b), name
+    # -0.0 is taken as +0.0, so it loses the z-buffer to every positive disparity as in the oracle
+    d = d0.copy()
+    d[10, 20] = -0.0
+    g.set_state(d, p0, f0)
+    got = _np(g.get_state()[0])
+    assert got[10, 20] == 0.0 and not np.signbit(got[10, 20])
+    F = O.OracleFilter(_oracle_params(seq))
+    F.set_state(d, p0, f0)
+    g.reduced_frame(seq.left[1], seq.right[1], seq.T[1])
+    F.reduced_frame(seq.left[1], seq.right[1], seq.T[1])
+    torch.cuda.synchronize()
+    _compare_state(g, F, "after -0.0 injection", True)

@@ -46,7 +46,7 @@ def test_median_of_planted_state(W, H, kind):
     d = _planted(W, H, W * 7 + H, kind)
     p = np.ones((H, W))
     sf = np.zeros((H, W), np.uint8)
-    g = sgmk.ReducedSGM(W, H, 128)
+    g = sgmk.ReducedSGM(W, H, 256)     # the planted impulses reach 200 px
     g.set_state(d, p, sf)
     got = g.disparity_median().cpu().numpy()
     want = O.median3x3(d).astype(np.float32)

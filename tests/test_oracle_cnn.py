@@ -342,3 +342,28 @@ def test_gate_rerun_measures_failed_pixels_over_the_full_range():
     b.predict_learned(seq.left[1], seq.T[1])
     b.finish_learned(seq.left[1], seq.right[1], hw, np.full(hw.shape, 0.25), gate_rerun=True)
     assert not b.gatefail.any() and not np.any(b.flags & oracle.GATEFAIL)
+
+
+def test_targets_hand_worked():
+    # training targets of a predicted frame, worked by hand:
+    #   e = dz_full - dhat (measurement minus prediction), m = dz_full - gt,
+    #   both clipped to +-16 px; we = prediction exists; wm = we and valid truth
+    dhat = np.array([[10.0, 10.0, 5.0, 0.0, 20.0, 3.25]])
+    flags = np.array([[oracle.PRED, oracle.PRED | oracle.RESET, 0, oracle.PRED, oracle.PRED,
+                       oracle.PRED | oracle.FULLWIN]], np.uint8)
+    dz_full = np.array([[12.5, 40.0, 7.0, 3.0, 0.0, 3.0]])
+    gt = np.array([[12.0, 13.0, 7.0, -1.0, 19.0, 20.0]])
+    valid = np.array([[True, True, True, False, True, True]])
+    e, m, we, wm = cnn.targets(dhat, flags, dz_full, gt, valid)
+    # pixel 0: +2.5 / +0.5; pixel 1: +30 -> +16 / +27 -> +16 (RESET keeps the prediction);
+    # pixel 2: no prediction -> all zero even though the truth is valid;
+    # pixel 3: +3 and no valid truth; pixel 4: -20 -> -16 / -19 -> -16;
+    # pixel 5: -0.25 and 3 - 20 = -17 -> -16
+    assert np.array_equal(e, [[2.5, 16.0, 0.0, 3.0, -16.0, -0.25]])
+    assert np.array_equal(m, [[0.5, 16.0, 0.0, 0.0, -16.0, -16.0]])
+    assert np.array_equal(we, [[1.0, 1.0, 0.0, 1.0, 1.0, 1.0]])
+    assert np.array_equal(wm, [[1.0, 1.0, 0.0, 0.0, 1.0, 1.0]])
+    # the clip is exactly +-16: 16 stays, 16.5 becomes 16
+    e, m, _, _ = cnn.targets(np.array([[0.0, 0.0]]), np.array([[oracle.PRED] * 2], np.uint8),
+                             np.array([[16.0, 16.5]]), np.array([[0.0, 0.5]]), np.array([[True, True]]))
+    assert np.array_equal(e, [[16.0, 16.0]]) and np.array_equal(m, [[16.0, 16.0]])

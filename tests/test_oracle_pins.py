@@ -584,3 +584,36 @@ def test_end_to_end_tiny_sequence_accuracy():
         F.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
         w = F.hi - F.lo + 1
         assert w.mean() < 0.5 * seq.max_disp        # the search space shrinks
+
+
+def test_wrong_ego_motion_is_detected_and_recovered():
+    # Section 2.4 / Section 4: with a wrong ego-motion (1.5 m of extra forward
+    # motion at frame 2) the prediction disagrees with the measurement: many
+    # predicted pixels are flagged moving and reset; the reset pixels search
+    # the full range in frame 3, and by frame 4 the estimate is no worse than
+    # that of the run that never had the error
+    seq = synth.make_sequence("tiny", frames=5)
+    prm = O.Params(seq.cam.width, seq.cam.height, seq.max_disp, f=seq.cam.f, baseline=seq.cam.baseline)
+
+    def run(corrupt):
+        F = O.OracleFilter(prm)
+        F.full_frame(seq.left[0], seq.right[0])
+        stats = []
+        for k in range(1, 5):
+            T = seq.T[k].copy()
+            if corrupt and k == 2:
+                T[2, 3] -= 1.5
+            F.reduced_frame(seq.left[k], seq.right[k], T)
+            v = seq.valid[k]
+            pred = (F.flags & O.PRED) != 0
+            stats.append(dict(bad=float(np.mean(np.abs(F.d - seq.disp_gt[k])[v] > 3)),
+                              mask=float(F.mask[pred].mean()), reset=float((F.sflags & O.RESET).astype(bool).mean()),
+                              full=float(((F.flags & O.FULLWIN) != 0).mean())))
+        return stats
+
+    clean, bad = run(False), run(True)
+    assert bad[0] == clean[0]
+    assert bad[1]["mask"] > 0.2 and bad[1]["mask"] > 5 * clean[1]["mask"]
+    assert bad[1]["reset"] > 0.1 and bad[1]["bad"] > 3 * clean[1]["bad"]
+    assert bad[2]["full"] > clean[2]["full"] + 0.1          # frame 3 re-measures the reset pixels
+    assert bad[3]["bad"] <= clean[3]["bad"] + 0.01          # recovered by frame 4
