@@ -392,6 +392,29 @@ int sgm_detect_frame(sgm_detector *det, sgm_context *ctx, int32_t *boxes, int32_
 enum { SGM_DSTAGE_SAT = 0, SGM_DSTAGE_FIRED = 1 };
 int sgm_detector_stage(sgm_detector *det, int32_t stage, void *out, size_t bytes, void *stream);
 
+/* Detection for callers that cannot allocate device memory: code under HIP
+ * graph capture, allocation-free serving loops, harnesses that forbid
+ * hipMalloc.  The same computation and outputs as sgm_detect (boxes,
+ * count[0..1] on the caller's device arrays, same layouts), without a
+ * detector object: the settings come in `prm` (sgm_detect_default_params
+ * gives the defaults) and the scratch (column prefixes, summed-area table,
+ * one byte per window) lives in one library-wide device array of
+ * SGM_DETECT_NOALLOC_BYTES on each GPU the call runs on, held until the
+ * process ends.  The call allocates nothing and frees nothing.
+ * Scratch need: rows * width * 4 + (rows + 1) * (width + 1) * 4 + windows
+ * bytes (rows = height - top), each part rounded up to 256; a larger need
+ * returns SGM_EINVAL without launching anything (1920x1080 with the
+ * default top = height / 3 needs 11 MB).  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (different streams without
+ * ordering, or several host threads) race and give undefined results;
+ * calls ordered on one stream are safe.  Every scratch byte a call reads is
+ * written earlier in the same call, so nothing needs clearing between
+ * calls.  SGM_EINVAL for NULL pointers and the settings sgm_detector_create
+ * rejects, SGM_EHIP if the launch fails. */
+#define SGM_DETECT_NOALLOC_BYTES (32u << 20)
+int sgm_detect_noalloc(int32_t width, int32_t height, const sgm_detect_params *prm, const double *dhat,
+                       const double *dz, const uint8_t *flags, int32_t *boxes, int32_t *count, void *stream);
+
 /* Thread-local message describing the last nonzero return on this thread. */
 const char *sgm_last_error(void);
 

@@ -33,7 +33,7 @@ EXPORTS = ("sgm_default_params", "sgm_paper_params", "sgm_create", "sgm_destroy"
            "sgm_cnn_set_params", "sgm_cnn_get_params", "sgm_cnn_forward", "sgm_cnn_loss", "sgm_cnn_backward",
            "sgm_cnn_get_grads", "sgm_cnn_adam", "sgm_cnn_train_step", "sgm_detect_default_params",
            "sgm_detector_create", "sgm_detector_destroy", "sgm_detector_windows", "sgm_detect", "sgm_detect_frame",
-           "sgm_detector_stage", "sgm_last_error")
+           "sgm_detector_stage", "sgm_detect_noalloc", "sgm_last_error")
 PROF_STAGES = ("census", "predict", "cost", "agg_h", "agg_v", "wta", "cnn", "rerun")
 
 
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
         "sgm_detect": [P, P, P, P, P, P, P],
         "sgm_detect_frame": [P, P, P, P, P],
         "sgm_detector_stage": [P, I32, P, SZ, P],
+        "sgm_detect_noalloc": [I32, I32, ctypes.POINTER(SgmDetectParams), P, P, P, P, P, P],
         "sgm_last_error": [],
     }
     for name, args in sig.items():

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "sgm_internal.h"
@@ -1698,3 +1699,68 @@ int sgm_detector_stage(sgm_detector *det, int32_t stage, void *out, size_t bytes
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// detection without allocation: the scratch is a file-scope device array
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[SGM_DETECT_NOALLOC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices];   // device address of `scratch` on each GPU (host-side name is not one)
+
+// Address of the current device's copy of `scratch`, looked up once per device.
+int scratch_of_current_device(uint8_t **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(SGM_EINVAL, "device %d outside 0..%d", dev, kMaxDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+        g_scratch[dev] = (uint8_t *)p;
+    }
+    *out = g_scratch[dev];
+    return SGM_OK;
+}
+
+size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" int sgm_detect_noalloc(int32_t width, int32_t height, const sgm_detect_params *prm, const double *dhat,
+                                  const double *dz, const uint8_t *flags, int32_t *boxes, int32_t *count,
+                                  void *stream)
+{
+    if (!prm)
+        return fail(SGM_EINVAL, "params is NULL");
+    if (!dhat || !dz || !flags || !boxes || !count)
+        return fail(SGM_EINVAL, "NULL input or output pointer");
+    DetectGeom dg;
+    const int64_t nwin = detect_geometry(width, height, prm, &dg);
+    if (nwin < 0)
+        return (int)nwin;
+    const size_t colp_b = round256((size_t)dg.rows * (size_t)width * sizeof(uint32_t));
+    const size_t sat_b = round256((size_t)(dg.rows + 1) * (size_t)(width + 1) * sizeof(uint32_t));
+    const size_t need = colp_b + sat_b + round256((size_t)(nwin > 0 ? nwin : 1));
+    if (need > (size_t)SGM_DETECT_NOALLOC_BYTES)
+        return fail(SGM_EINVAL, "%dx%d with top %d needs %zu bytes of scratch, more than the %u available", width,
+                    height, prm->top, need, (unsigned)SGM_DETECT_NOALLOC_BYTES);
+    uint8_t *base = nullptr;
+    int rc = scratch_of_current_device(&base);
+    if (rc)
+        return rc;
+    uint32_t *colp = (uint32_t *)base;
+    uint32_t *sat = (uint32_t *)(base + colp_b);
+    uint8_t *fire = base + colp_b + sat_b;
+    hipError_t e = launch_detect(dg, dhat, dz, flags, colp, sat, fire, boxes, count, as_stream(stream));
+    return e == hipSuccess ? SGM_OK : hip_fail(e, "detection launch");
+}
