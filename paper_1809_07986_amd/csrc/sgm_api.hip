@@ -107,6 +107,7 @@ void free_buffers(DevBuffers &b)
     void *all[] = {b.cen_l,  b.cen_r, b.win,    b.off,   b.scan_part, b.cost,  b.lr,    b.sum,     b.d,
                    b.p,      b.sflags, b.mask,  b.dhat,  b.pm,        b.flags, b.dstar, b.dz,      b.zkey,
                    b.zidx,   b.tgt,   b.dprime, b.pprime, b.has,      b.rw,    b.dw,    b.pw,      b.status,
+                   b.widened,
                    b.hflag,  b.nu,    b.nu_w,   b.feat,  b.act_a,     b.act_b, b.cnn_out, b.hw,    b.rpix,
                    b.theta,  b.frag};
     for (void *p : all)
@@ -215,7 +216,8 @@ int start_census(sgm_context *ctx, const uint8_t *l, const uint8_t *r, int32_t p
 
 // cost (debug), aggregation, WTA (+ filter update in modes 0 and 1) on the
 // census start_census launched for this frame
-int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true)
+// skip: a gate re-run pass, whose launches do nothing when *skip == 0
+int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true, const uint32_t *skip = nullptr)
 {
     const Geometry &g = ctx->g;
     DevBuffers &b = ctx->b;
@@ -243,13 +245,13 @@ int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true)
             return hip_fail(e, "stream fork");
         StageMark mh(marks ? ctx->prof : g_noprof, ctx->side);
         mh.begin(SGM_PROF_AGG_H);
-        e = launch_agg_h(g, b, mode == 0, ctx->side);
+        e = launch_agg_h(g, b, mode == 0, ctx->side, skip);
         mh.end(SGM_PROF_AGG_H);
         if (e != hipSuccess)
             return hip_fail(e, "horizontal aggregation launch");
     }
     mk.begin(SGM_PROF_AGG_V);
-    e = launch_agg_v(g, b, mode == 0, s);
+    e = launch_agg_v(g, b, mode == 0, s, skip);
     mk.end(SGM_PROF_AGG_V);
     if (e != hipSuccess)
         return hip_fail(e, "aggregation launch");
@@ -262,7 +264,7 @@ int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true)
     }
     mk.begin(SGM_PROF_WTA);
     const float *rpix = (mode == 1 && ctx->prm.window_mode == SGM_WIN_LEARNED) ? b.rpix : nullptr;
-    e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, rpix, s);
+    e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, rpix, s, skip);
     mk.end(SGM_PROF_WTA);
     if (e != hipSuccess)
         return hip_fail(e, "wta launch");
@@ -320,14 +322,16 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
         return rc;
     if (p.gate_rerun) {
         // pixels that failed the innovation test search the full range in a
-        // second matching pass and restart from its measurement
+        // second matching pass and restart from its measurement; with no such
+        // pixel the pass would reproduce the first one, and its launches read
+        // the device-side count and return at once
         mk.begin(SGM_PROF_RERUN);
         e = launch_gate_widen(ctx->g, ctx->b, s);
         if (e == hipSuccess)
-            e = launch_scan(ctx->g, ctx->b, s);
+            e = launch_scan(ctx->g, ctx->b, s, ctx->b.widened);
         if (e != hipSuccess)
             return hip_fail(e, "gate re-run launch");
-        rc = run_matcher(ctx, 1, s, false);
+        rc = run_matcher(ctx, 1, s, false, ctx->b.widened);
         mk.end(SGM_PROF_RERUN);
         if (rc)
             return rc;
@@ -459,6 +463,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.flags, N));
     A(dalloc(&b.dstar, N));
     A(dalloc(&b.dz, N));
+    A(dalloc(&b.widened, 1));
     A(dalloc(&b.zkey, N));
     A(dalloc(&b.zidx, N));
     A(dalloc(&b.tgt, N));

@@ -41,6 +41,7 @@ struct DevBuffers {
     uint8_t *has, *rw;
     double *dw, *pw;
     uint32_t *status;
+    uint32_t *widened;         // pixels widened by the innovation test in this frame (gate re-run)
     uint8_t *hflag;            // horizontal aggregation: flagged segments [2][H][kHMaxSeg]
     // learned window (allocated in learned mode only, except nu / nu_w)
     double *nu;                // innovation of the last frame (0 without prediction)
@@ -88,16 +89,18 @@ hipError_t launch_cost(const Geometry &g, DevBuffers &b, hipStream_t s);
 // independent and may run on different streams.
 int count_horizontal_paths(const Geometry &g);
 // dense: every window is the full range (the full-frame kernels)
-hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s);
-hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s);
+// skip: when not NULL, the launches of a second (gate re-run) pass read *skip on
+// the device and do nothing when it is 0 (no pixel was widened)
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip = nullptr);
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip = nullptr);
 // mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only;
 // rpix: per-pixel measurement variance (NULL: cc.r)
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, const float *rpix, hipStream_t s);
+                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip = nullptr);
 // prediction without the offset scan (launch_predict = this + launch_scan)
 hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
                                const CorrectConst &cc, hipStream_t s);
-hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s, const uint32_t *skip = nullptr);
 
 // learned window (sgm_cnn.hip)
 size_t cnn_frag_count();

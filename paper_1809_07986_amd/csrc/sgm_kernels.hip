@@ -38,6 +38,10 @@ __device__ __forceinline__ int row_min16(int v)
     return v;
 }
 
+// a launch of a gate re-run pass with no widened pixel does nothing: that pass
+// would reproduce the first one
+__device__ __forceinline__ bool pass_skipped(const uint32_t *skip) { return skip && *skip == 0u; }
+
 // order LDS traffic of the lanes of one wave (no instruction beyond waits)
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -188,7 +192,7 @@ __global__ void k_given_windows(int N, int D, const int32_t *lo, const int32_t *
     flags[p] = (lc == 0 && hc == D - 1) ? SGM_FLAG_FULLWIN : 0;
 }
 
-hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s);
+hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s, const uint32_t *skip);
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
@@ -204,7 +208,7 @@ hipError_t launch_given_windows(const Geometry &g, DevBuffers &b, const int32_t 
     e = hipGetLastError();
     if (e != hipSuccess)
         return e;
-    return launch_scan(g, b, s);
+    return launch_scan(g, b, s, nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -448,7 +452,7 @@ hipError_t launch_predict(const Geometry &g, DevBuffers &b, const WarpConst &wc,
     hipError_t e = launch_predict_core(g, b, wc, Tdev, cc, s);
     if (e != hipSuccess)
         return e;
-    return launch_scan(g, b, s);
+    return launch_scan(g, b, s, nullptr);
 }
 
 hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
@@ -509,8 +513,10 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *total)
 // each block adds the sums of the blocks before it to its own exclusive scan
 // (the block sums are few, so every block reads them all).
 __global__ __launch_bounds__(SCAN_T) void k_scan_sums(int N, const uint16_t *__restrict__ win,
-                                                      uint32_t *__restrict__ part)
+                                                      uint32_t *__restrict__ part, const uint32_t *skip)
 {
+    if (pass_skipped(skip))
+        return;
     __shared__ uint32_t tot;
     const int base = blockIdx.x * SCAN_BLOCK + threadIdx.x * SCAN_PER;
     uint32_t sum = 0;
@@ -526,8 +532,10 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_sums(int N, const uint16_t *__r
 
 __global__ __launch_bounds__(SCAN_T) void k_scan_apply(int N, const uint16_t *__restrict__ win,
                                                        uint32_t *__restrict__ off,
-                                                       const uint32_t *__restrict__ part)
+                                                       const uint32_t *__restrict__ part, const uint32_t *skip)
 {
+    if (pass_skipped(skip))
+        return;
     __shared__ uint32_t tot, before_tot;
     // sum of the block sums before this block
     uint32_t pre = 0;
@@ -556,11 +564,11 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_apply(int N, const uint16_t *__
         off[N] = before + tot;
 }
 
-hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s)
+hipError_t launch_scan(const Geometry &g, DevBuffers &b, hipStream_t s, const uint32_t *skip)
 {
     int nparts = (g.N + SCAN_BLOCK - 1) / SCAN_BLOCK;   // <= SCAN_BLOCK, checked at create
-    hipLaunchKernelGGL(k_scan_sums, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.scan_part);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.off, b.scan_part);
+    hipLaunchKernelGGL(k_scan_sums, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.scan_part, skip);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nparts), dim3(SCAN_T), 0, s, g.N, b.win, b.off, b.scan_part, skip);
     return hipGetLastError();
 }
 
@@ -669,7 +677,9 @@ struct AggArgs {
     int8_t slot[kMaxPaths];   // output buffer index of each listed path
     int kmin[kMaxPaths];      // first chain index of each listed path (k_agg_v)
     uint8_t *hflag;           // horizontal segments whose two trajectories never met [path][H][AH2_MAXSEG]
+    const uint32_t *skip;     // when not NULL and *skip == 0 the launch does nothing (gate re-run pass)
 };
+
 
 constexpr int LBIG = 0x3FFF;   // "absent" predecessor term (> any L_r + P1)
 
@@ -852,6 +862,8 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int l)
 template <int MAXCH>
 __global__ __launch_bounds__(64) void k_agg_h(AggArgs a, int raise_prio)
 {
+    if (pass_skipped(a.skip))
+        return;
     // with ragged windows at D > 128 this is the longer of the two concurrent
     // aggregation streams: its waves win issue arbitration (with dense
     // windows the vertical kernel is the longer one)
@@ -1256,6 +1268,8 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
 template <int MAXD>
 __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
 {
+    if (pass_skipped(a.skip))
+        return;
     const int pi = blockIdx.y;
     // this kernel runs beside the horizontal passes on a second stream: at
     // D <= 128 it is the longer of the two and its waves win issue
@@ -1311,6 +1325,8 @@ __host__ __device__ constexpr size_t agg_h2_lds(int D, int G)
 template <int MODE, int G>
 __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
 {
+    if (pass_skipped(a.skip))
+        return;
     constexpr int NGG = AH2_T / G;                          // groups of G lanes per block
     constexpr int NC = MODE == HS_FIX ? NGG / 2 : NGG;       // scanlines per block
     // staged census loads per thread: 16-lane groups serve D <= 128, 32-lane groups D <= 256
@@ -1564,9 +1580,11 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
     }
 }
 
-static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv, int &nh, int &nv, int &maxv)
+static void agg_args(const Geometry &g, DevBuffers &b, AggArgs &hv, AggArgs &vv, int &nh, int &nv, int &maxv,
+                     const uint32_t *skip)
 {
     for (AggArgs *a : {&hv, &vv}) {
+        a->skip = skip;
         a->cl = b.cen_l;
         a->cr = b.cen_r;
         a->win = b.win;
@@ -1644,11 +1662,11 @@ static hipError_t launch_agg_h2(const Geometry &g, const AggArgs &hv, int nh, hi
     return hipGetLastError();
 }
 
-hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s)
+hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip)
 {
     AggArgs hv, vv;
     int nh, nv, maxv;
-    agg_args(g, b, hv, vv, nh, nv, maxv);
+    agg_args(g, b, hv, vv, nh, nv, maxv, skip);
     if (!nh)
         return hipSuccess;
     // Ragged windows: segmented scanlines (16 lanes per pixel, many waves)
@@ -1671,11 +1689,11 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s)
+hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip)
 {
     AggArgs hv, vv;
     int nh, nv, maxv;
-    agg_args(g, b, hv, vv, nh, nv, maxv);
+    agg_args(g, b, hv, vv, nh, nv, maxv, skip);
     if (!nv)
         return hipSuccess;
     if (dense) {
@@ -1734,8 +1752,11 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        int32_t *__restrict__ dstar_out, double *__restrict__ dz_out,
                                                        double *__restrict__ d_state, double *__restrict__ p_state,
                                                        uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags,
-                                                       const float *__restrict__ rpix, double *__restrict__ nu_out)
+                                                       const float *__restrict__ rpix, double *__restrict__ nu_out,
+                                                       const uint32_t *skip)
 {
+    if (pass_skipped(skip))
+        return;
     constexpr int WNG = WTA_T / WG;   // pixels per block
     extern __shared__ uint16_t ssum_lds[];   // [WNG][D + 8] cost sums of each pixel's window
     const int grp = threadIdx.x / WG, lane = threadIdx.x % WG;
@@ -1834,20 +1855,20 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
 }
 
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, const float *rpix, hipStream_t s)
+                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip)
 {
     if (mode == 0)
         hipLaunchKernelGGL((k_wta_correct<16>), dim3((g.N + 15) / 16), dim3(WTA_T), (size_t)16 * (g.D + 8) * 2, s,
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu);
+                       b.nu, skip);
     else
         hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), (size_t)32 * (g.D + 8) * 2, s,
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu);
+                       b.nu, skip);
     return hipGetLastError();
 }
 

@@ -283,12 +283,12 @@ def test_learned_targets_match_oracle():
 
 # ---------------------------------------------------------------- learned frames
 
-def _learned_run(seq, theta, gate_rerun, frames=(1, 2), label=""):
+def _learned_run(seq, theta, gate_rerun, frames=(1, 2), label="", **over):
     kw = dict(f=seq.cam.f, baseline=seq.cam.baseline)
     g = sgmk.ReducedSGM(seq.cam.width, seq.cam.height, seq.max_disp, window_mode=NAT.WIN_LEARNED,
-                        gate_rerun=int(gate_rerun), **kw)
+                        gate_rerun=int(gate_rerun), **kw, **over)
     g.set_window_model(theta)
-    o = O.OracleFilter(_prm(seq))
+    o = O.OracleFilter(_prm(seq, **over))
     g.full_frame(seq.left[0], seq.right[0])
     o.full_frame(seq.left[0], seq.right[0])
     th_ref = _gpu_reference_theta(theta)
@@ -332,6 +332,17 @@ def test_learned_frames_match_oracle(gate_rerun):
     stats = _learned_run(seq, _theta(3, o0_bias=0.5, o1_bias=-1.0), gate_rerun, label=f"rerun={gate_rerun}")
     if gate_rerun:
         assert any(s["gatefail"] > 0 for s in stats), "the moving box should fail the innovation test"
+
+
+def test_learned_rerun_without_failures_matches_oracle():
+    # no pixel can fail the innovation test (the gate is out of reach), so the
+    # second matching pass has nothing to widen: the library's re-run launches
+    # return at once, the oracle re-runs, and the two must still agree
+    _say("learned frames, tiny, gate_rerun=True, unreachable gate")
+    seq = _seq()
+    stats = _learned_run(seq, _theta(3, o0_bias=0.5, o1_bias=-1.0), True, label="rerun, no failure",
+                         chi2_gate=1e300)
+    assert all(s["gatefail"] == 0 for s in stats)
 
 
 def test_learned_frame_full_size_matches_oracle():
