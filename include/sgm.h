@@ -74,6 +74,15 @@ typedef struct {
     int32_t gate_rerun;         /* 1: pixels failing the innovation test are matched again over
                                    the full range in the same frame and restart from that
                                    measurement (the frame is matched twice) */
+    double r_curv;              /* 0: every pixel's measurement variance is r.  > 0 (SGM_WIN_KSIGMA
+                                   contexts): the variance of a pixel's measurement is estimated
+                                   from the cost values at the neighbouring disparities (Section 3,
+                                   the approach of the authors' earlier method):
+                                   r_pix = r_curv / kappa clamped to [1/256, 64], with
+                                   kappa = S(d*-1) + S(d*+1) - 2 S(d*) >= 1 the curvature of the
+                                   sub-pixel parabola, and r_pix = r where d* lies on a window
+                                   edge; r_pix enters the gain and the innovation test; a pixel
+                                   restarting from its measurement takes p = r */
 } sgm_params;
 
 /* Fill `out` with the defaults for a width x height x max_disp problem:
@@ -172,7 +181,11 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
  *   SGM_STAGE_FEATURES       bfloat16 [4] per pixel: network input
  *   SGM_STAGE_CNN_OUT        float32 [2] per pixel: network output
  *   SGM_STAGE_HALFWIDTH      float32 per pixel: half-width w
- *   SGM_STAGE_RPIX           float32 per pixel: measurement variance r
+ *   SGM_STAGE_RPIX           float32 per pixel: measurement variance r (also in
+ *                            r_curv > 0 contexts: the curvature estimate, last frame)
+ * curvature measurement variance (r_curv > 0 contexts, last frame):
+ *   SGM_STAGE_KAPPA          int32 per pixel: kappa of the sub-pixel parabola, 0 where
+ *                            d* lies on a window edge
  * sgm_cost_cells() synchronises the stream and returns the cell count M. */
 enum {
     SGM_STAGE_CENSUS_L = 0, SGM_STAGE_CENSUS_R, SGM_STAGE_LO, SGM_STAGE_HI, SGM_STAGE_OFFSETS,
@@ -180,7 +193,7 @@ enum {
     SGM_STAGE_DSTAR, SGM_STAGE_DZ, SGM_STAGE_STATUS,
     SGM_STAGE_PATH0 = 16,
     SGM_STAGE_NU = 32, SGM_STAGE_NU_W, SGM_STAGE_FEATURES, SGM_STAGE_CNN_OUT, SGM_STAGE_HALFWIDTH,
-    SGM_STAGE_RPIX
+    SGM_STAGE_RPIX, SGM_STAGE_KAPPA
 };
 int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream);
 int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);

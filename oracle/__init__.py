@@ -96,6 +96,7 @@ class Params:
     cx: Optional[float] = None
     cy: Optional[float] = None
     baseline: float = 0.54
+    r_curv: float = 0.0     # > 0: per-pixel measurement variance r_curv / kappa (curvature_r); not in the C struct
 
     def __post_init__(self):
         if self.cx is None:
@@ -133,6 +134,7 @@ def _load():
             lib.orc_predict_aux.argtypes = [P] * 12
             lib.orc_learned_windows.argtypes = [P] * 6
             lib.orc_correct_ex.argtypes = [P] * 14
+            lib.orc_curvature_r.argtypes = [P, i, i, i, P, P, P, ctypes.c_double, ctypes.c_double, P, P]
             lib.orc_median3x3.argtypes = [P, i, i, P]
             lib.orc_motion_values.argtypes = [P, P, P, i, i, i, i, P]
             lib.orc_integral.argtypes = [P, i, i, P]
@@ -291,6 +293,21 @@ def correct_ex(prm: Params, dhat, pm, flags, lo, hi, dstar, dz, rpix=None):
     return d, p, mask, sflags, nu
 
 
+def curvature_r(S, lo, hi, dstar, r_curv: float, r_const: float):
+    """Per-pixel measurement variance from the cost curvature kappa = a + b
+    of the sub-pixel parabola: r = clamp(r_curv / kappa, 1/256, 64), r_const
+    where d* lies on a window edge (kappa = 0).  S dense [H, W, D].
+    -> (rpix float64, kappa int32)."""
+    S = _c(S, np.int32)
+    lo, hi, dstar = _c(lo, np.int32), _c(hi, np.int32), _c(dstar, np.int32)
+    H, W, D = S.shape
+    rpix = np.zeros((H, W), np.float64)
+    kappa = np.zeros((H, W), np.int32)
+    _check(_load().orc_curvature_r(_p(S), W, H, D, _p(lo), _p(hi), _p(dstar), float(r_curv), float(r_const),
+                                   _p(rpix), _p(kappa)), "curvature_r")
+    return rpix, kappa
+
+
 def median3x3(d) -> np.ndarray:
     """3x3 block median with clamped borders (Section 2.3 post-processing)."""
     d = _c(d, np.float64)
@@ -424,6 +441,21 @@ class OracleFilter:
 
     def full_frame(self, left, right):
         left, right = _c(left, np.uint8), _c(right, np.uint8)
+        if self.prm.r_curv > 0:
+            # as orc_full_frame, keeping the sums for the curvature of each pixel
+            D = self.prm.max_disp
+            self.lo[:] = 0
+            self.hi[:] = D - 1
+            self.dstar, self.dz, _, S = match(self.prm, left, right, self.lo, self.hi, want_cs=True)
+            self.rpix, self.kappa = curvature_r(S, self.lo, self.hi, self.dstar, self.prm.r_curv, self.prm.r)
+            self.d[:] = self.dz
+            self.p[:] = self.prm.r
+            self.sflags[:] = 0
+            self.mask[:] = 0
+            self.flags[:] = FULLWIN
+            self.nu[:] = 0.0
+            self.started = True
+            return
         cp = self.prm.c()
         _check(_load().orc_full_frame(ctypes.byref(cp), _p(left), _p(right), _p(self.d), _p(self.p),
                                       _p(self.sflags), _p(self.mask), _p(self.lo), _p(self.hi),
@@ -437,6 +469,14 @@ class OracleFilter:
             raise RuntimeError("reduced_frame before full_frame")
         left, right = _c(left, np.uint8), _c(right, np.uint8)
         T = _c(T, np.float64).reshape(16)
+        if self.prm.r_curv > 0:
+            # predict, match keeping the sums, correct with the curvature variance
+            self.dhat, self.pm, self.flags, self.lo, self.hi = predict(self.prm, self.d, self.p, self.sflags, T)
+            self.dstar, self.dz, _, S = match(self.prm, left, right, self.lo, self.hi, want_cs=True)
+            self.rpix, self.kappa = curvature_r(S, self.lo, self.hi, self.dstar, self.prm.r_curv, self.prm.r)
+            self.d, self.p, self.mask, self.sflags, self.nu = correct_ex(
+                self.prm, self.dhat, self.pm, self.flags, self.lo, self.hi, self.dstar, self.dz, self.rpix)
+            return
         cp = self.prm.c()
         _check(_load().orc_reduced_frame(ctypes.byref(cp), _p(left), _p(right), _p(T), _p(self.d),
                                          _p(self.p), _p(self.sflags), _p(self.mask), _p(self.dhat),

@@ -543,6 +543,42 @@ int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, 
     return 0;
 }
 
+/* ------------------------------------------------------------------------
+ * Per-pixel measurement variance from the cost curvature.  Section 3 says the
+ * authors' earlier method estimated the measurement noise from the cost
+ * values at the neighbouring disparities, without a formula.  Reading: near
+ * its minimum the aggregated cost is a negative log-likelihood up to a scale,
+ *     S(d) ~ S(d*) + kappa (d - d_z)^2 / 2,
+ * with kappa = a + b = S(d*-1) + S(d*+1) - 2 S(d*), the second difference
+ * through the three sums of the sub-pixel parabola (kappa >= 1, since a >= 1
+ * by the lowest-disparity tie rule); the measurement variance is then
+ *     r = r_curv / kappa,   clamped to [1/256, 64],
+ * with r_curv (cost units x px^2) a parameter fitted to ground truth.  Where
+ * the parabola is not defined (d* on a window edge) kappa = 0 and
+ * r = r_const.  S is dense [H][W][D] (only window cells are read).
+ * ---------------------------------------------------------------------- */
+int orc_curvature_r(const int32_t *S, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+                    const int32_t *dstar, double r_curv, double r_const, double *rpix, int32_t *kappa)
+{
+    for (int p = 0; p < W * H; p++) {
+        const int32_t *s = S + (size_t)p * D;
+        const int ds = dstar[p];
+        int k = 0;
+        double r = r_const;
+        if (ds - 1 >= lo[p] && ds + 1 <= hi[p]) {
+            k = (s[ds - 1] - s[ds]) + (s[ds + 1] - s[ds]);
+            r = r_curv / (double)k;
+            if (r < 1.0 / 256.0)
+                r = 1.0 / 256.0;
+            if (r > 64.0)
+                r = 64.0;
+        }
+        rpix[p] = r;
+        kappa[p] = k;
+    }
+    return 0;
+}
+
 /* Learned search windows: a pixel that still has a finite window after the
  * prediction gets [floor(dhat - w), ceil(dhat + w)] clipped to [0, D-1],
  * with w its predicted half-width; w >= ORC_LEARNED_WMAX (or NaN) sends it to

@@ -44,6 +44,8 @@ int orc_predict(const orc_params *prm, const double *d, const double *p, const u
 int orc_predict_aux(const orc_params *prm, const double *d, const double *p, const uint8_t *sflags,
                     const double *aux_src, const double T[16], double *dhat, double *pm, uint8_t *flags,
                     int32_t *lo, int32_t *hi, double *aux_out);
+int orc_curvature_r(const int32_t *S, int W, int H, int D, const int32_t *lo, const int32_t *hi,
+                    const int32_t *dstar, double r_curv, double r_const, double *rpix, int32_t *kappa);
 int orc_learned_windows(const orc_params *prm, const double *dhat, const double *hw, uint8_t *flags,
                         int32_t *lo, int32_t *hi);
 int orc_correct_ex(const orc_params *prm, const double *dhat, const double *pm, const uint8_t *flags,

@@ -20,7 +20,7 @@ CNN_NPARAMS = 19394
 (STAGE_CENSUS_L, STAGE_CENSUS_R, STAGE_LO, STAGE_HI, STAGE_OFFSETS, STAGE_COST, STAGE_SUM, STAGE_DHAT,
  STAGE_PM, STAGE_FLAGS, STAGE_DSTAR, STAGE_DZ, STAGE_STATUS) = range(13)
 STAGE_PATH0 = 16
-(STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX) = range(32, 38)
+(STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX, STAGE_KAPPA) = range(32, 39)
 
 # every symbol include/sgm.h declares
 EXPORTS = ("sgm_default_params", "sgm_paper_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",
@@ -44,7 +44,8 @@ class SgmParams(ctypes.Structure):
                 ("k_sigma", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
                 ("chi2_gate", ctypes.c_double), ("disc_thresh", ctypes.c_double),
                 ("f", ctypes.c_double), ("cx", ctypes.c_double), ("cy", ctypes.c_double),
-                ("baseline", ctypes.c_double), ("window_mode", ctypes.c_int32), ("gate_rerun", ctypes.c_int32)]
+                ("baseline", ctypes.c_double), ("window_mode", ctypes.c_int32), ("gate_rerun", ctypes.c_int32),
+                ("r_curv", ctypes.c_double)]
 
 
 class SgmDetectParams(ctypes.Structure):

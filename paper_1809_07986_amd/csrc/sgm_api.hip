@@ -93,6 +93,10 @@ int validate(const sgm_params *p)
         return fail(SGM_EINVAL, "window_mode %d is neither SGM_WIN_KSIGMA nor SGM_WIN_LEARNED", p->window_mode);
     if (p->gate_rerun != 0 && p->gate_rerun != 1)
         return fail(SGM_EINVAL, "gate_rerun must be 0 or 1 (got %d)", p->gate_rerun);
+    if (!(p->r_curv >= 0) || !isfinite(p->r_curv))
+        return fail(SGM_EINVAL, "r_curv must be finite and >= 0");
+    if (p->r_curv > 0 && p->window_mode == SGM_WIN_LEARNED)
+        return fail(SGM_EINVAL, "r_curv > 0 needs SGM_WIN_KSIGMA windows (the learned window predicts r)");
     return SGM_OK;
 }
 
@@ -108,7 +112,7 @@ void free_buffers(DevBuffers &b)
                    b.p,      b.sflags, b.mask,  b.dhat,  b.pm,        b.flags, b.dstar, b.dz,      b.zkey,
                    b.zidx,   b.tgt,   b.dprime, b.pprime, b.has,      b.rw,    b.dw,    b.pw,      b.status,
                    b.widened,
-                   b.hflag,  b.nu,    b.nu_w,   b.feat,  b.act_a,     b.act_b, b.cnn_out, b.hw,    b.rpix,
+                   b.hflag,  b.nu,    b.nu_w,   b.feat,  b.act_a,     b.act_b, b.cnn_out, b.hw,    b.rpix,  b.kappa,
                    b.theta,  b.frag};
     for (void *p : all)
         if (p)
@@ -144,6 +148,7 @@ CorrectConst correct_const(const sgm_params &p)
     c.gate = p.chi2_gate;
     c.k_sigma = p.k_sigma;
     c.disc = p.disc_thresh;
+    c.curv = p.r_curv;
     return c;
 }
 
@@ -263,6 +268,7 @@ int run_matcher(sgm_context *ctx, int mode, hipStream_t s, bool marks = true, co
             return hip_fail(e, "stream join");
     }
     mk.begin(SGM_PROF_WTA);
+    // per-pixel measurement variance: the learned window's (read) or the cost curvature's (written)
     const float *rpix = (mode == 1 && ctx->prm.window_mode == SGM_WIN_LEARNED) ? b.rpix : nullptr;
     e = launch_wta_correct(g, b, correct_const(ctx->prm), mode, ctx->debug, rpix, s, skip);
     mk.end(SGM_PROF_WTA);
@@ -486,6 +492,10 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
         A(dalloc(&b.rpix, N));
         A(dalloc(&b.theta, (size_t)SGM_CNN_NPARAMS));
         A(dalloc(&b.frag, cnn_frag_count()));
+    }
+    if (prm->r_curv > 0) {
+        A(dalloc(&b.rpix, N));
+        A(dalloc(&b.kappa, N));
     }
     if (e != hipSuccess) {
         free_buffers(b);
@@ -820,12 +830,18 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
     case SGM_STAGE_CNN_OUT:
     case SGM_STAGE_HALFWIDTH:
     case SGM_STAGE_RPIX:
-        if (ctx->prm.window_mode != SGM_WIN_LEARNED)
+        if (ctx->prm.window_mode != SGM_WIN_LEARNED && !(stage == SGM_STAGE_RPIX && ctx->prm.r_curv > 0))
             return fail(SGM_EINVAL, "stage %d exists in learned-window contexts only", stage);
         src = stage == SGM_STAGE_FEATURES ? (const void *)b.feat
               : stage == SGM_STAGE_CNN_OUT ? (const void *)b.cnn_out
               : stage == SGM_STAGE_HALFWIDTH ? (const void *)b.hw : (const void *)b.rpix;
         need = stage == SGM_STAGE_FEATURES || stage == SGM_STAGE_CNN_OUT ? N * 8 : N * 4;
+        break;
+    case SGM_STAGE_KAPPA:
+        if (!(ctx->prm.r_curv > 0))
+            return fail(SGM_EINVAL, "SGM_STAGE_KAPPA exists in r_curv > 0 contexts only");
+        src = b.kappa;
+        need = N * 4;
         break;
     case SGM_STAGE_LO:
     case SGM_STAGE_HI: {

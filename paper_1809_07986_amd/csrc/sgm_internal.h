@@ -50,6 +50,7 @@ struct DevBuffers {
     uint16_t *act_a, *act_b;   // activations, bfloat16 [N][32] each
     float *cnn_out;            // network output [N][2]
     float *hw, *rpix;          // half-width and measurement variance per pixel
+    int32_t *kappa;            // curvature of the sub-pixel parabola (r_curv > 0 contexts)
     float *theta;              // network parameters (fp32)
     uint64_t *frag;            // bfloat16 MFMA operands of the parameters
 };
@@ -72,6 +73,7 @@ struct WarpConst {
 
 struct CorrectConst {
     double r, gate, k_sigma, disc;
+    double curv;           // > 0: per-pixel r = curv / kappa of the sub-pixel parabola (clamped)
 };
 
 // kernel launchers (all asynchronous on `s`); return hipError_t of the launch

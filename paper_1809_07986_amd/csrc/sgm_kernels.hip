@@ -1753,7 +1753,8 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        double *__restrict__ d_state, double *__restrict__ p_state,
                                                        uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags,
                                                        const float *__restrict__ rpix, double *__restrict__ nu_out,
-                                                       const uint32_t *skip)
+                                                       const uint32_t *skip, float *__restrict__ rcurv_out,
+                                                       int32_t *__restrict__ kappa_out)
 {
     if (pass_skipped(skip))
         return;
@@ -1814,15 +1815,24 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     const int s0 = (int)(key >> 9);
     const int ds = lo + slot;
     double dz = (double)ds;
+    int kappa = 0;   // curvature a + b of the parabola (0: d* on a window edge)
     if (ds - 1 >= lo && ds + 1 <= hi) {
         const int a = (int)ssum[slot - 1] - s0, b = (int)ssum[slot + 1] - s0;
         dz = (double)ds + (double)(a - b) / (double)(2 * (a + b));
+        kappa = a + b;
     }
     dstar_out[t] = ds;
     dz_out[t] = dz;
+    double r = rpix ? (double)rpix[t] : cc.r;
+    if (cc.curv > 0.0) {
+        // measurement variance from the cost curvature: curv / kappa in [1/256, 64]
+        if (kappa > 0)
+            r = fmin(fmax(cc.curv / (double)kappa, 1.0 / 256.0), 64.0);
+        kappa_out[t] = kappa;
+        rcurv_out[t] = (float)r;
+    }
     if (mode == 2)
         return;
-    const double r = rpix ? (double)rpix[t] : cc.r;
     bool moving = false;
     double nu = 0.0, S = 0.0;
     if (fl & SGM_FLAG_PRED) {
@@ -1862,13 +1872,13 @@ hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectCon
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu, skip);
+                       b.nu, skip, b.rpix, b.kappa);
     else
         hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), (size_t)32 * (g.D + 8) * 2, s,
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu, skip);
+                       b.nu, skip, b.rpix, b.kappa);
     return hipGetLastError();
 }
 

@@ -16,7 +16,17 @@ Both variances are the mean squared error of the errors within +-`inlier`
 pixels (gross mismatches and warp outliers are counted separately), with the
 fraction of errors inside +-1 px and the histograms.
 
-    python -m paper_1809_07986_amd.estimate_noise --out gpurun_out/noise.json
+Per-pixel measurement noise from the cost curvature (the approach Section 3
+attributes to the authors' earlier method): the library's r_curv mode gives
+each measurement the variance r_curv / kappa, kappa the curvature of the
+sub-pixel parabola.  With the errors e of the full-range measurements taken
+as N(0, tau / kappa), the maximum-likelihood tau is mean(e^2 kappa) over the
+inliers; it is reported with the constant r.  --compare then runs the filter
+on the same sequences with the constant default r, the constant estimated r
+and the curvature variance with the estimated tau, and reports the
+bad-pixel rates (> 3 px on valid truth) of the filtered disparity.
+
+    python -m paper_1809_07986_amd.estimate_noise --compare --out gpurun_out/noise.json
 """
 from __future__ import annotations
 
@@ -75,11 +85,50 @@ def process_errors(g, seq, k: int, T: np.ndarray, torch, N) -> np.ndarray:
     return (dhat - seq.disp_gt[k].astype(np.float64))[use]
 
 
-def measurement_errors(g, seq, k: int, N) -> np.ndarray:
+def measurement_errors(g, seq, k: int, N):
+    """Full-range measurement minus the truth on static pixels, and the
+    curvature kappa of each of those measurements (g has r_curv > 0)."""
     g.full_frame(seq.left[k], seq.right[k])
     dz = g.stage(N.STAGE_DZ).cpu().numpy()
+    kappa = g.stage(N.STAGE_KAPPA).cpu().numpy()
     use = seq.valid[k] & ~seq.mover[k]
-    return (dz - seq.disp_gt[k].astype(np.float64))[use]
+    return (dz - seq.disp_gt[k].astype(np.float64))[use], kappa[use]
+
+
+def curvature_scale(err: np.ndarray, kappa: np.ndarray, inlier: float = 3.0) -> dict:
+    """Maximum-likelihood tau of e ~ N(0, tau / kappa) over the inliers with a
+    defined curvature: tau = mean(e^2 kappa)."""
+    use = (kappa > 0) & (np.abs(err) <= inlier)
+    e, k = err[use].astype(np.float64), kappa[use].astype(np.float64)
+    tau = float(np.mean(e * e * k))
+    return {"tau": tau, "n": int(use.sum()), "kappa_median": float(np.median(k)),
+            "r_median": float(np.median(np.clip(tau / k, 1 / 256, 64.0)))}
+
+
+def filter_accuracy(sgmk, N, seqs, torch, label: str, **params) -> dict:
+    """Bad-pixel rate (> 3 px on valid truth) and mean |error| of the filtered
+    disparity and of the measurement, frames 1.. of each sequence."""
+    bad_d = bad_z = n = 0
+    abs_d = 0.0
+    for seq in seqs:
+        H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+        g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, **params)
+        g.full_frame(seq.left[0], seq.right[0])
+        for k in range(1, seq.frames):
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+            d = g.get_state()[0].cpu().numpy()
+            dz = g.stage(N.STAGE_DZ).cpu().numpy()
+            gt = seq.disp_gt[k].astype(np.float64)
+            v = seq.valid[k]
+            bad_d += int((np.abs(d - gt)[v] > 3).sum())
+            bad_z += int((np.abs(dz - gt)[v] > 3).sum())
+            abs_d += float(np.abs(d - gt)[v].sum())
+            n += int(v.sum())
+        g.close()
+    res = {"bad_px_gt3_d": bad_d / n, "bad_px_gt3_dz": bad_z / n, "mean_abs_err_d": abs_d / n, "pixels": n}
+    print(f"  {label}: bad d {res['bad_px_gt3_d']:.5f}, bad dz {res['bad_px_gt3_dz']:.5f}, "
+          f"mean |d - gt| {res['mean_abs_err_d']:.4f}", flush=True)
+    return res
 
 
 def main(argv=None):
@@ -90,6 +139,8 @@ def main(argv=None):
     ap.add_argument("--ego-rot-deg", default="0,0.02,0.05", help="rotation noise levels (deg)")
     ap.add_argument("--ego-trans-m", type=float, default=0.01, help="translation noise when rotation noise > 0")
     ap.add_argument("--inlier", type=float, default=3.0)
+    ap.add_argument("--compare", action="store_true",
+                    help="filter accuracy with constant r, estimated r and the curvature variance")
     ap.add_argument("--out", default=os.path.join("gpurun_out", "noise.json"))
     args = ap.parse_args(argv)
     import torch
@@ -99,27 +150,45 @@ def main(argv=None):
     seeds = [int(s) for s in args.seeds.split(",")]
     levels = [float(v) for v in args.ego_rot_deg.split(",")]
     proc = {lv: [] for lv in levels}
-    meas = []
+    meas, kap = [], []
+    seqs = []
     for seed in seeds:
         seq = make_sequence("driving", frames=args.frames, seed=seed)
+        seqs.append(seq)
         H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
         g = sgmk.ReducedSGM(W, H, D, preset=args.preset, f=seq.cam.f, baseline=seq.cam.baseline)
+        gc = sgmk.ReducedSGM(W, H, D, preset=args.preset, f=seq.cam.f, baseline=seq.cam.baseline, r_curv=1.0)
         rng = np.random.default_rng(seed)
         for k in range(1, seq.frames):
             for lv in levels:
                 T = perturb(seq.T[k], rng, lv, args.ego_trans_m if lv > 0 else 0.0)
                 proc[lv].append(process_errors(g, seq, k, T, torch, N))
-            meas.append(measurement_errors(g, seq, k, N))
+            e, kp = measurement_errors(gc, seq, k, N)
+            meas.append(e)
+            kap.append(kp)
         g.close()
+        gc.close()
         print(f"  sequence {seed} done", flush=True)
     res = {"seeds": seeds, "frames": args.frames, "preset": args.preset, "inlier_px": args.inlier,
            "process": {f"rot {lv:g} deg" + (f", trans {args.ego_trans_m:g} m" if lv > 0 else " (exact ego-motion)"):
                        noise_stats(np.concatenate(v), args.inlier) for lv, v in proc.items()},
-           "measurement": noise_stats(np.concatenate(meas), args.inlier)}
+           "measurement": noise_stats(np.concatenate(meas), args.inlier),
+           "curvature": curvature_scale(np.concatenate(meas), np.concatenate(kap), args.inlier)}
     for k, v in res["process"].items():
         print(f"  q [{k}]: {v['variance']:.4f} px^2, within 1 px {v['within_1px']:.4f}, outliers {v['outliers']:.4f}")
     m = res["measurement"]
     print(f"  r: {m['variance']:.4f} px^2, within 1 px {m['within_1px']:.4f}, outliers {m['outliers']:.4f}")
+    c = res["curvature"]
+    print(f"  curvature: tau {c['tau']:.3f} (cost x px^2), median kappa {c['kappa_median']:g}, "
+          f"median r {c['r_median']:.4f} px^2", flush=True)
+    if args.compare:
+        res["compare"] = {
+            "constant r = 1 (default)": filter_accuracy(sgmk, N, seqs, torch, "constant r = 1", preset=args.preset),
+            f"constant r = {m['variance']:.4f} (estimated)": filter_accuracy(
+                sgmk, N, seqs, torch, "constant estimated r", preset=args.preset, r=m["variance"]),
+            f"curvature, tau = {c['tau']:.3f}": filter_accuracy(
+                sgmk, N, seqs, torch, "curvature r", preset=args.preset, r_curv=c["tau"]),
+        }
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     with open(args.out, "w") as fh:
         json.dump(res, fh, indent=1)

@@ -242,6 +242,19 @@ def test_paper_preset_sequence(mask):
     _run_sequence(seq, seq.frames, f"tiny paper preset mask={mask:#x}", preset="paper", path_mask=mask)
 
 
+@pytest.mark.parametrize("preset,frames,tau", [("tiny", 3, 20.0), ("driving", 3, 8.0)])
+def test_curvature_measurement_variance_sequence(preset, frames, tau):
+    # per-pixel measurement variance from the curvature of the sub-pixel
+    # parabola (r_curv > 0): kappa, r and the filter state against the oracle
+    seq = synth.make_sequence(preset, frames=frames)
+    g, F = _run_sequence(seq, frames, f"{preset} r_curv={tau}", r_curv=tau)
+    kappa = _np(g.stage(NAT.STAGE_KAPPA))
+    assert np.array_equal(kappa, F.kappa)
+    assert np.array_equal(_np(g.stage(NAT.STAGE_RPIX)), F.rpix.astype(np.float32))
+    assert (kappa > 0).mean() > 0.5 and len(np.unique(F.rpix)) > 10
+    _say(f"  kappa median {np.median(kappa[kappa > 0])}, r median {np.median(F.rpix):.4f}")
+
+
 def test_injected_state_prediction_stage():
     # the oracle's state is injected, so prediction parity does not depend on
     # earlier frames; includes RESET flags and a lateral + yaw motion
@@ -273,7 +286,8 @@ def test_reduced_before_full_is_an_error():
 
 def test_invalid_params_rejected():
     for kw in (dict(p1=90, p2=80), dict(census_w=11, census_h=7), dict(path_mask=0),
-               dict(max_disp=300), dict(r=0.0)):
+               dict(max_disp=300), dict(r=0.0), dict(r_curv=-1.0), dict(r_curv=float("nan")),
+               dict(r_curv=2.0, window_mode=NAT.WIN_LEARNED)):
         md = kw.pop("max_disp", 32)
         with pytest.raises(sgmk.SgmError) as e:
             sgmk.ReducedSGM(32, 16, md, **kw)

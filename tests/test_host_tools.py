@@ -41,3 +41,18 @@ def test_perturb_keeps_a_rigid_motion():
     assert abs(np.linalg.det(R) - 1.0) < 1e-12
     assert np.array_equal(P[3], [0, 0, 0, 1])
     assert not np.allclose(P, T)
+
+
+def test_curvature_scale_recovers_tau():
+    # errors drawn as N(0, tau / kappa): the maximum-likelihood scale mean(e^2 kappa)
+    # returns tau within its sampling error (relative sd sqrt(2/n))
+    from paper_1809_07986_amd.estimate_noise import curvature_scale
+    rng = np.random.default_rng(3)
+    n, tau = 200000, 7.5
+    kappa = rng.integers(20, 400, n)
+    err = rng.normal(0.0, np.sqrt(tau / kappa))
+    kappa[:1000] = 0                       # undefined curvature: not used
+    err[1000:1100] = 50.0                  # gross errors beyond the inlier bound: not used
+    res = curvature_scale(err, kappa, inlier=3.0)
+    assert res["n"] == n - 1100
+    assert abs(res["tau"] / tau - 1) < 5 * np.sqrt(2 / res["n"])

@@ -317,6 +317,66 @@ def test_subpixel_edges_and_range():
     assert np.all(off[edge] == 0.0)
 
 
+# ------------------------------------------------- cost-curvature measurement variance
+
+@pytest.mark.parametrize("c,e", [(1, 0), (3, 2), (7, -5), (40, 39), (200, -17)])
+def test_curvature_of_a_parabola_is_its_second_difference(c, e):
+    # S(d) = 50 + c (d - m)^2 + e (d - m) with |e| < c has its integer minimum
+    # at m, and the three samples around it have a = c - e, b = c + e: the
+    # curvature a + b = 2c whatever the slope e, and r = r_curv / (2c)
+    D, m = 16, 7
+    dd = np.arange(D)
+    S = (50 + c * (dd - m) ** 2 + e * (dd - m)).astype(np.int32).reshape(1, 1, D)
+    lo, hi = np.zeros((1, 1), np.int32), np.full((1, 1), D - 1, np.int32)
+    dstar, _ = O.wta(S, lo, hi)
+    assert dstar[0, 0] == m
+    tau = 3.5
+    rpix, kappa = O.curvature_r(S, lo, hi, dstar, tau, 1.0)
+    assert kappa[0, 0] == 2 * c
+    want = min(max(tau / (2 * c), 1 / 256), 64.0)
+    assert rpix[0, 0] == want
+
+
+def test_curvature_edges_ties_and_clamps():
+    D = 8
+    lo = np.array([[0, 2, 0, 0, 3]], np.int32)
+    hi = np.array([[7, 2, 7, 7, 5]], np.int32)
+    S = np.full((1, 5, D), 90, np.int32)
+    S[0, 0, 0:3] = [10, 20, 30]                  # minimum on the lower edge: no parabola
+    S[0, 1, 2] = 5                                # one-cell window
+    S[0, 2, 2:6] = [40, 30, 30, 60]               # tie: d* = 3 (lowest), a = 10, b = 0
+    S[0, 3, 3:6] = [12, 11, 12]                   # kappa = 2: r_curv / 2 above 64 -> 64
+    S[0, 4, 3:6] = [80, 70, 60]                   # minimum on the upper edge
+    dstar, _ = O.wta(S, lo, hi)
+    assert dstar.tolist() == [[0, 2, 3, 4, 5]]
+    rpix, kappa = O.curvature_r(S, lo, hi, dstar, 1000.0, 0.75)
+    assert kappa.tolist() == [[0, 0, 10, 2, 0]]
+    assert rpix[0, 0] == 0.75 and rpix[0, 1] == 0.75 and rpix[0, 4] == 0.75
+    assert rpix[0, 2] == 64.0 and rpix[0, 3] == 64.0
+    rpix, _ = O.curvature_r(S, lo, hi, dstar, 0.001, 0.75)
+    assert rpix[0, 2] == 1 / 256 and rpix[0, 3] == 1 / 256
+
+
+def test_curvature_filter_uses_the_per_pixel_variance():
+    # a filter run with r_curv: the correction of each pixel is the Kalman
+    # closed form with that pixel's r = clamp(r_curv / kappa)
+    seq = synth.make_sequence("tiny")
+    H, W, D = seq.cam.height, seq.cam.width, seq.max_disp
+    F = O.OracleFilter(O.Params(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, r_curv=20.0))
+    F.full_frame(seq.left[0], seq.right[0])
+    assert np.all(F.p == F.prm.r) and np.all(F.d == F.dz)
+    k = F.kappa
+    assert np.all((k == 0) | (k >= 1))
+    F.reduced_frame(seq.left[1], seq.right[1], seq.T[1])
+    r = np.where(F.kappa > 0, np.clip(20.0 / np.maximum(F.kappa, 1), 1 / 256, 64.0), F.prm.r)
+    assert np.array_equal(F.rpix, r)
+    use = ((F.flags & O.PRED) != 0) & ((F.flags & O.FULLWIN) == 0)
+    assert use.sum() > 1000
+    r, pm, dh, dz = r[use], F.pm[use], F.dhat[use], F.dz[use]
+    assert np.max(np.abs(F.d[use] - (r * dh + pm * dz) / (pm + r))) < 1e-9
+    assert np.max(np.abs(F.p[use] / (pm * r / (pm + r)) - 1)) < 1e-9
+
+
 # ---------------------------------------------------------------- prediction
 
 def _prm(H=24, W=32, D=64, **kw):
