@@ -211,9 +211,10 @@ def main():
     ap.add_argument("--cpu-frames-1t", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--skip-full", action="store_true", help="skip the full-range comparison (profiling runs)")
-    ap.add_argument("--workload", choices=("driving", "batched", "learned"), default="driving",
+    ap.add_argument("--workload", choices=("driving", "batched", "learned", "combined"), default="driving",
                     help="driving: one 1242x375x128 stream (the headline); batched: 16 uneven streams; "
-                         "learned: learned vs k-sigma windows at 1242x375x256")
+                         "learned: learned vs k-sigma windows at 1242x375x256; combined: 4 x 1920x1080x256 "
+                         "learned + batched vs full range")
     ap.add_argument("--no-learned", action="store_true", help="omit the learned-window section")
     ap.add_argument("--learned-steps", type=int, default=200)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -230,6 +231,8 @@ def main():
 
     if args.workload == "batched":
         return bench_batched(args)
+    if args.workload == "combined":
+        return bench_combined(args)
     if args.workload == "learned":
         res = bench_learned(args)
         out = {"metric": "frames/s and cost-cells/s, learned vs k-sigma windows at 1242×375×256, 1 GPU",
@@ -549,76 +552,200 @@ BATCH_STREAMS = ([dict(width=640, height=480, max_disp=64)] * 4 + [dict(width=12
                  + [dict(width=1920, height=1080, max_disp=256)] * 4)
 
 
+BATCH_FRAMES = 10
+
+
+def _render_streams(cfgs, seeds, frames, **over):
+    """Render one seeded sequence per stream configuration (in parallel processes)."""
+    from concurrent.futures import ProcessPoolExecutor
+    from stereo_synth import make_sequence
+    jobs = []
+    with ProcessPoolExecutor(max_workers=min(8, len(cfgs))) as ex:
+        for cfg, seed in zip(cfgs, seeds):
+            kw = dict(over)
+            kw.update(width=cfg["width"], height=cfg["height"], max_disp=cfg["max_disp"], f=cfg["f"])
+            jobs.append(ex.submit(make_sequence, kw.pop("preset", "driving"), frames, seed, None, False, **kw))
+        return [j.result() for j in jobs]
+
+
+def _batch_step_bytes(cells: int, pixels: int) -> int:
+    # per-step algorithmic bytes of the whole batch: 28 B per cost cell (eight
+    # paths with on-the-fly costs) plus about 100 B per pixel (prediction,
+    # windows, correction)
+    return 28 * cells + 100 * pixels
+
+
+def _time_batch(b, sched, Tsteps, Ls, Rs, first, count, full=False):
+    import torch
+    n = len(Ls)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record()
+    for j in range(first, first + count):
+        _, k = sched[j]
+        for i in range(n):
+            b.left[i].copy_(Ls[i][k])
+            b.right[i].copy_(Rs[i][k])
+        b.step(None if full else Tsteps[j])
+    ev1.record()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / count, ev0.elapsed_time(ev1) / count
+
+
 def bench_batched(args):
     """16 independent streams of uneven size (4 x 640x480 D64, 8 x 1242x375
-    D128, 4 x 1920x1080 D256) stepped together over concurrent lanes, schedule
-    chosen by the library's autotuner; the same steps with every stream run one
-    after another (one lane) are timed as the unbatched reference.  Each stream has 3 rendered frames, visited
-    0->1->2->1->0...; a step = one steady-state frame of every stream."""
+    D128, 4 x 1920x1080 D256), 10 rendered frames each visited
+    0->1->..->9->8->..; a step = one steady-state frame of every stream, run
+    over concurrent lanes with the schedule the library's autotuner picks
+    (lanes, order, horizontal segment length and kernel).  The same steps
+    with every stream run one after another (one lane) are the unbatched
+    reference.  Input copies into the batch's buffers are inside the timed
+    region (device to device)."""
     import torch
     import paper_1809_07986_amd as sgmk
-    from stereo_synth import make_sequence
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
-    seqs, cfgs = [], []
-    for i, st in enumerate(BATCH_STREAMS):
-        W, H, D = st["width"], st["height"], st["max_disp"]
-        f = 0.58 * W if W != 1242 else 720.0
-        seqs.append(make_sequence("driving", frames=3, seed=300 + i, width=W, height=H, max_disp=D, f=f))
-        cfgs.append(dict(width=W, height=H, max_disp=D, f=f, baseline=0.54))
+    cfgs = []
+    for st in BATCH_STREAMS:
+        W = st["width"]
+        cfgs.append(dict(width=W, height=st["height"], max_disp=st["max_disp"],
+                         f=0.58 * W if W != 1242 else 720.0, baseline=0.54))
+    seqs = _render_streams(cfgs, [300 + i for i in range(len(cfgs))], BATCH_FRAMES)
     Ls = [torch.from_numpy(q.left).to(dev) for q in seqs]
     Rs = [torch.from_numpy(q.right).to(dev) for q in seqs]
     n = len(seqs)
-    sched = frame_schedule(3, args.warmup + args.steps + 1)
-    Tsteps = [sgmk.SgmBatch._Ts(np.stack([T_between(q, a, b) for q in seqs])) for a, b in sched]
+    sched = frame_schedule(BATCH_FRAMES, args.warmup + args.steps + 1)
+    Tsteps = [sgmk.SgmBatch._Ts(np.stack([T_between(q, a, c) for q in seqs])) for a, c in sched]
     b = sgmk.SgmBatch(cfgs)
     for i in range(n):
         b.left[i].copy_(Ls[i][0])
         b.right[i].copy_(Rs[i][0])
     b.full()
-    # autotune on the first step's inputs (restores the filter state)
-    a0, b0 = sched[0]
+    _, k0 = sched[0]
     for i in range(n):
-        b.left[i].copy_(Ls[i][b0])
-        b.right[i].copy_(Rs[i][b0])
-    lanes, order = b.autotune(Tsteps[0], reps=3)
-
-    def run(step_fn, first, count):
-        for j in range(first, first + count):
-            a_, b_ = sched[j]
-            for i in range(n):
-                b.left[i].copy_(Ls[i][b_])
-                b.right[i].copy_(Rs[i][b_])
-            step_fn(Tsteps[j])
-
-    run(b.step, 0, args.warmup)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run(b.step, args.warmup, args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+        b.left[i].copy_(Ls[i][k0])
+        b.right[i].copy_(Rs[i][k0])
+    lanes, order, hseg, halt = b.autotune(Tsteps[0], reps=2)   # restores the filter state
+    _time_batch(b, sched, Tsteps, Ls, Rs, 0, args.warmup)
+    dt, dt_ev = _time_batch(b, sched, Tsteps, Ls, Rs, args.warmup, args.steps)
     cells = sum(c.cost_cells() for c in b.contexts)
+    pixels = sum(c["width"] * c["height"] for c in cfgs)
     b.set_schedule(1, 0)
-    run(b.step, 0, 2)
-    torch.cuda.synchronize()
     nser = min(args.steps, 30)
-    t0 = time.perf_counter()
-    run(b.step, args.warmup, nser)
-    torch.cuda.synchronize()
-    dte = (time.perf_counter() - t0) / nser
+    _time_batch(b, sched, Tsteps, Ls, Rs, 0, 2)
+    dte, _ = _time_batch(b, sched, Tsteps, Ls, Rs, args.warmup, nser)
     full_cells = sum(c["width"] * c["height"] * c["max_disp"] for c in cfgs)
+    byt = _batch_step_bytes(cells, pixels)
+    gbs = byt / (dt_ev * 1e-3) / 1e9
     out = {
         "metric": "stream-frames/s and cost-cells/s, 16 uneven streams batched, 1 GPU",
-        "value": round(n * args.steps / dt, 2), "unit": "stream-frames/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "value": round(n / dt, 2), "unit": "stream-frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": "batched: 4x640x480 D64, 8x1242x375 D128, 4x1920x1080 D256, census 9x7, 8 paths, "
-                               "streams over concurrent lanes", "schedule": {"lanes": lanes, "order": order}},
+        "config": {"workload": "batched: 4x640x480 D64, 8x1242x375 D128, 4x1920x1080 D256, 10 frames each, "
+                               "census 9x7, 8 paths, streams over concurrent lanes",
+                   "schedule": {"lanes": lanes, "order": order, "h_segment": hseg, "h_kernel_alt": halt}},
         "cost_cells_last_step": cells, "full_range_cells_per_step": full_cells,
-        "cost_cells_per_s_estimate": round(cells * args.steps / dt, 1),
-        "serial_ms_per_step": round(dte * 1e3, 4),
-        "speedup_vs_serial": round(dte / (dt / args.steps), 3),
+        "cost_cells_per_s_estimate": round(cells / dt, 1),
+        "serial_ms_per_step": round(dte * 1e3, 4), "speedup_vs_serial": round(dte / dt, 3),
+        "roofline": {"bound": "hbm", "kernel": "whole batch step (every stream's kernels)",
+                     "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                     "traffic": None, "algorithmic_bytes_per_step": byt,
+                     "byte_model": "28 B/cell (8 paths, cost on the fly) + 100 B/pixel",
+                     "avg_step_ms": round(dt_ev, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_combined(args):
+    """Large combined workload: 4 concurrent 1920x1080 streams, disparities
+    0-255, 10 moving cars, ego-motion 1.5 m/frame with yaw <= 3 deg; learned
+    windows with the gate re-run, batched over lanes (autotuned schedule),
+    against plain full-range SGM on the same streams; bad pixels (> 3 px on
+    valid truth) of both over one pass of the frames."""
+    import torch
+    import paper_1809_07986_amd as sgmk
+    from paper_1809_07986_amd import _native as N
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    W, H, D, nst = 1920, 1080, 256, 4
+    cfgs = [dict(width=W, height=H, max_disp=D, f=0.58 * W, baseline=0.54) for _ in range(nst)]
+    seqs = _render_streams(cfgs, [500 + i for i in range(nst)], BATCH_FRAMES, preset="learned", cars=10,
+                           speed=1.5, yaw=3.0, near=2.4)
+    Ls = [torch.from_numpy(q.left).to(dev) for q in seqs]
+    Rs = [torch.from_numpy(q.right).to(dev) for q in seqs]
+    sched = frame_schedule(BATCH_FRAMES, args.warmup + args.steps + 1)
+    Tsteps = [sgmk.SgmBatch._Ts(np.stack([T_between(q, a, c) for q in seqs])) for a, c in sched]
+    theta = sgmk.load_window_model()
+    b = sgmk.SgmBatch([dict(c, window_mode=N.WIN_LEARNED, gate_rerun=1) for c in cfgs])
+    for c in b.contexts:
+        c.set_window_model(theta)
+    for i in range(nst):
+        b.left[i].copy_(Ls[i][0])
+        b.right[i].copy_(Rs[i][0])
+    b.full()
+    # accuracy pass: learned (reduced) frames 1..9 vs full range on the same frames
+    bad = {"learned": 0, "full_range": 0}
+    npx = 0
+    cells_l = []
+    bf = sgmk.SgmBatch(cfgs)
+    for k in range(1, BATCH_FRAMES):
+        for i in range(nst):
+            b.left[i].copy_(Ls[i][k])
+            b.right[i].copy_(Rs[i][k])
+            bf.left[i].copy_(Ls[i][k])
+            bf.right[i].copy_(Rs[i][k])
+        b.step(sgmk.SgmBatch._Ts(np.stack([q.T[k] for q in seqs])))
+        bf.full()
+        cells_l.append(sum(c.cost_cells() for c in b.contexts))
+        for i, q in enumerate(seqs):
+            gt, v = q.disp_gt[k].astype(np.float64), q.valid[k]
+            dl = b.contexts[i].get_state()[0].cpu().numpy()
+            df = bf.contexts[i].get_state()[0].cpu().numpy()
+            bad["learned"] += int((np.abs(dl - gt)[v] > 3).sum())
+            bad["full_range"] += int((np.abs(df - gt)[v] > 3).sum())
+            npx += int(v.sum())
+    # restart for timing: full frame 0, tune, then time reduced steps
+    for i in range(nst):
+        b.left[i].copy_(Ls[i][0])
+        b.right[i].copy_(Rs[i][0])
+    b.full()
+    _, k0 = sched[0]
+    for i in range(nst):
+        b.left[i].copy_(Ls[i][k0])
+        b.right[i].copy_(Rs[i][k0])
+    lanes, order, hseg, halt = b.autotune(Tsteps[0], reps=2)
+    _time_batch(b, sched, Tsteps, Ls, Rs, 0, args.warmup)
+    dt, dt_ev = _time_batch(b, sched, Tsteps, Ls, Rs, args.warmup, args.steps)
+    cells = sum(c.cost_cells() for c in b.contexts)
+    bf.set_schedule(nst, 1)
+    _time_batch(bf, sched, Tsteps, Ls, Rs, 0, 2, full=True)
+    nfull = min(args.steps, 30)
+    dtf, _ = _time_batch(bf, sched, Tsteps, Ls, Rs, args.warmup, nfull, full=True)
+    byt = _batch_step_bytes(cells, nst * W * H)
+    gbs = byt / (dt_ev * 1e-3) / 1e9
+    out = {
+        "metric": "stream-frames/s, learned-window reduced SGM batched vs full-range SGM, 4x1920x1080x256, 1 GPU",
+        "value": round(nst / dt, 2), "unit": "stream-frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": "combined: 4 streams 1920x1080, disparities 0-255, 10 moving cars, 1.5 m/frame, "
+                               "yaw <= 3 deg, learned windows + gate re-run, batched, 10 frames each",
+                   "schedule": {"lanes": lanes, "order": order, "h_segment": hseg, "h_kernel_alt": halt}},
+        "cells_per_step": cells, "mean_cells_per_step_accuracy_pass": round(float(np.mean(cells_l)), 1),
+        "full_range_cells_per_step": nst * W * H * D,
+        "full_range": {"stream_frames_per_s": round(nst / dtf, 2), "ms_per_step": round(dtf * 1e3, 4)},
+        "speedup_vs_full_range": round(dtf / dt, 3),
+        "bad_px_gt3": {"learned": round(bad["learned"] / npx, 6), "full_range": round(bad["full_range"] / npx, 6),
+                       "frames": f"1-{BATCH_FRAMES - 1} of each stream"},
+        "roofline": {"bound": "hbm", "kernel": "whole batch step (every stream's kernels)",
+                     "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                     "traffic": None, "algorithmic_bytes_per_step": byt,
+                     "byte_model": "28 B/cell (8 paths, cost on the fly) + 100 B/pixel",
+                     "avg_step_ms": round(dt_ev, 4)},
     }
     print(json.dumps(out), flush=True)
 

@@ -304,32 +304,49 @@ int sgm_cnn_train_step(sgm_cnn *t, const uint16_t *x, const float *targets, int3
  * batch's lifetime; write each new frame into them, stream-ordered, before
  * the step).  Per-step ego-motions go through device memory.
  *
- * sgm_batch_create: n streams, params[i], left[i], right[i] device buffers,
- *   pitch[i] bytes.  Allocates everything (contexts, lanes, save area).
+ * sgm_batch_create: n streams with params[i]; left[i], right[i] (device) and
+ *   pitch[i] (bytes) are stream i's default image buffers, used by steps that
+ *   pass no images and by graph replays.  Allocates everything (contexts,
+ *   lanes, save area, the batch's capture stream).
  * sgm_batch_context: stream i's context (outputs, state, stages); owned by
  *   the batch.
- * sgm_batch_full: full-range frame of every stream (Section 2.4 start).
- * sgm_batch_step: steady-state frame of every stream; T is a HOST array of
- *   n row-major 4x4 matrices.  SGM_ESTATE before sgm_batch_full.
- * sgm_batch_step_graph: stepping as a captured HIP graph.  Disabled: always
- *   returns SGM_EINVAL (its first run crashed the host process during stream
- *   capture; the cause has not been shown).
+ * sgm_batch_step: one frame of every stream.  left / right / pitch: arrays of
+ *   n device image pointers and pitches for this step, or NULL for the
+ *   default buffers.  T: HOST array of n row-major 4x4 ego-motions; stream i
+ *   runs a full-range frame (the filter's start, Section 2.4) when T is NULL
+ *   or its row has T[16 i + 15] == 0 (not a rigid motion), otherwise a
+ *   steady-state frame with that ego-motion.  SGM_ESTATE for a steady-state
+ *   frame of a stream that never had a full-range frame.
+ * sgm_batch_full: every stream full range (sgm_batch_step with T NULL and
+ *   the default images).
+ * sgm_batch_step_graph: stepping from a captured HIP graph.  Disabled:
+ *   always returns SGM_EINVAL (capturing a batch step, whose streams fork
+ *   onto lanes and side streams with events, crashed the host process inside
+ *   hipStreamEndCapture; the cause has not been shown).
  * sgm_batch_set_schedule: lanes (1..16) and order (0: streams as given,
  *   round-robin; 1: largest full-range work first onto the least-loaded lane).
- * sgm_batch_autotune: times every (lanes, order) candidate over `reps` steps
- *   with ego-motions T, keeps the fastest (written to chosen[0], chosen[1]
- *   when not NULL) and restores every stream's filter state and motion mask
- *   (the per-frame stages of sgm_get_stage show the last trial step);
- *   synchronises the stream. */
+ * sgm_autotune: chooses lanes, order and the horizontal aggregation schedule
+ *   of every stream (scanline segment length 48/72/96/128 and kernel family)
+ *   by timing steady-state steps on the default images with the last
+ *   ego-motions, for about budget_ms milliseconds in all; every candidate
+ *   starts from the streams' saved filter state and the state is restored at
+ *   the end.  Waits for the device (synchronous).  SGM_ESTATE without a
+ *   previous steady-state step.
+ * sgm_batch_autotune: the same with explicit ego-motions T and `reps` timed
+ *   steps per candidate; writes lanes, order, segment length and kernel
+ *   family to chosen[0..3] when not NULL; synchronises `stream`.
+ * (The stages of sgm_get_stage show the last trial step after autotuning.) */
 typedef struct sgm_batch sgm_batch;
 int sgm_batch_create(int32_t n, const sgm_params *params, const uint8_t *const *left,
                      const uint8_t *const *right, const int32_t *pitch, sgm_batch **out);
 void sgm_batch_destroy(sgm_batch *b);
 sgm_context *sgm_batch_context(sgm_batch *b, int32_t i);
+int sgm_batch_step(sgm_batch *b, const uint8_t *const *left, const uint8_t *const *right, const int32_t *pitch,
+                   const double *T, void *stream);
 int sgm_batch_full(sgm_batch *b, void *stream);
-int sgm_batch_step(sgm_batch *b, const double *T, void *stream);
 int sgm_batch_step_graph(sgm_batch *b, const double *T, void *stream);
 int sgm_batch_set_schedule(sgm_batch *b, int32_t lanes, int32_t order);
+int sgm_autotune(sgm_batch *b, int32_t budget_ms);
 int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *chosen, void *stream);
 
 /* ---- moving-object detection (Section 4) --------------------------------

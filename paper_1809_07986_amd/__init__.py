@@ -471,17 +471,33 @@ class SgmBatch:
     def full(self):
         _check(_lib().sgm_batch_full(self._h, _stream()))
 
-    def step(self, Ts):
-        _check(_lib().sgm_batch_step(self._h, self._Ts(Ts), _stream()))
+    def step(self, Ts, images=None):
+        """One frame of every stream.  Ts: n ego-motions (a row whose [3, 3]
+        entry is 0 runs a full-range frame), or None for all full range.
+        images: optional list of (left, right) device uint8 tensors for this
+        step (default: the batch's own buffers)."""
+        l = r = p = None
+        if images is not None:
+            ims = [(_dev_image(a, self.device), _dev_image(b, self.device)) for a, b in images]
+            l = (ctypes.c_void_p * self.n)(*[a.data_ptr() for a, _ in ims])
+            r = (ctypes.c_void_p * self.n)(*[b.data_ptr() for _, b in ims])
+            p = (ctypes.c_int32 * self.n)(*[a.stride(0) for a, _ in ims])
+            self._keep = ims
+        T = None if Ts is None else self._Ts(Ts)
+        _check(_lib().sgm_batch_step(self._h, l, r, p, T, _stream()))
 
     def step_graph(self, Ts):
-        """Captured-graph stepping (currently disabled in the library: raises)."""
+        """Captured-graph stepping (disabled in the library: raises SgmError)."""
         _check(_lib().sgm_batch_step_graph(self._h, self._Ts(Ts), _stream()))
 
     def set_schedule(self, lanes: int, order: int):
         _check(_lib().sgm_batch_set_schedule(self._h, lanes, order))
 
     def autotune(self, Ts, reps: int = 3):
-        chosen = (ctypes.c_int32 * 2)()
+        """-> (lanes, order, horizontal segment length, horizontal kernel family)."""
+        chosen = (ctypes.c_int32 * 4)()
         _check(_lib().sgm_batch_autotune(self._h, self._Ts(Ts), reps, chosen, _stream()))
-        return int(chosen[0]), int(chosen[1])
+        return tuple(int(v) for v in chosen)
+
+    def autotune_budget(self, budget_ms: int):
+        _check(_lib().sgm_autotune(self._h, int(budget_ms)))

@@ -28,7 +28,7 @@ EXPORTS = ("sgm_default_params", "sgm_paper_params", "sgm_create", "sgm_destroy"
            "sgm_get_state", "sgm_set_state",
            "sgm_match_windows", "sgm_get_stage", "sgm_cost_cells", "sgm_set_debug", "sgm_set_profiling",
            "sgm_read_profile", "sgm_batch_create", "sgm_batch_destroy", "sgm_batch_context", "sgm_batch_full",
-           "sgm_batch_step", "sgm_batch_step_graph", "sgm_batch_set_schedule", "sgm_batch_autotune",
+           "sgm_batch_step", "sgm_batch_step_graph", "sgm_batch_set_schedule", "sgm_batch_autotune", "sgm_autotune",
            "sgm_set_window_model", "sgm_get_features", "sgm_learned_targets", "sgm_cnn_create", "sgm_cnn_destroy",
            "sgm_cnn_set_params", "sgm_cnn_get_params", "sgm_cnn_forward", "sgm_cnn_loss", "sgm_cnn_backward",
            "sgm_cnn_get_grads", "sgm_cnn_adam", "sgm_cnn_train_step", "sgm_detect_default_params",
@@ -94,10 +94,12 @@ def load(path: str = LIB_PATH):
         "sgm_batch_destroy": [P],
         "sgm_batch_context": [P, I32],
         "sgm_batch_full": [P, P],
-        "sgm_batch_step": [P, ctypes.POINTER(ctypes.c_double), P],
+        "sgm_batch_step": [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(ctypes.c_double),
+                           P],
         "sgm_batch_step_graph": [P, ctypes.POINTER(ctypes.c_double), P],
         "sgm_batch_set_schedule": [P, I32, I32],
         "sgm_batch_autotune": [P, ctypes.POINTER(ctypes.c_double), I32, ctypes.POINTER(I32), P],
+        "sgm_autotune": [P, I32],
         "sgm_set_window_model": [P, ctypes.POINTER(ctypes.c_float), I32],
         "sgm_get_features": [P, P, I32, P, P],
         "sgm_learned_targets": [P, P, P, P, P],

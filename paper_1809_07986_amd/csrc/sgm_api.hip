@@ -889,18 +889,20 @@ struct sgm_batch {
     int n = 0;
     int device = 0;
     sgm_context **ctx = nullptr;
-    const uint8_t **left = nullptr, **right = nullptr;
+    const uint8_t **left = nullptr, **right = nullptr;   // default image buffers
     int32_t *pitch = nullptr;
-    double *Tdev = nullptr;                 // n x 16, device
+    double *Tdev = nullptr;                 // n x 16, device: the last ego-motions
+    bool have_T = false;                    // Tdev holds a steady-state step's ego-motions
     double *save_d = nullptr, *save_p = nullptr, *save_nu = nullptr;   // state save area for autotuning
     uint8_t *save_f = nullptr, *save_m = nullptr;
     size_t *save_off = nullptr;             // per-stream offsets into the save area
     int nlanes = 1;
     int order = 1;                          // 0: as given, 1: longest-processing-time first
+    int hseg = 72, halt = 0;                // horizontal schedule of every stream
     hipStream_t lane[kMaxLanes];
     hipEvent_t fork, join[kMaxLanes];
     int *lane_of = nullptr, *seq = nullptr; // lane per stream, launch order
-    bool started = false;
+    hipStream_t cap = nullptr;              // the batch's own stream (autotuning)
 };
 
 namespace {
@@ -935,30 +937,44 @@ void batch_schedule(sgm_batch *b)
         for (int i = 0; i < b->n; i++)
             b->lane_of[i] = i % b->nlanes;
     }
+    for (int i = 0; i < b->n; i++) {
+        b->ctx[i]->g.hseg = b->hseg;
+        b->ctx[i]->g.halt = b->halt != 0;
+    }
 }
 
-// enqueue one step of every stream on the lanes, forked from and joined
-// back into `s`; T comes from b->Tdev (reduced) or is unused (full)
-int batch_enqueue(sgm_batch *b, bool full, hipStream_t s)
+// a row of T whose homogeneous entry is 0 (no rigid motion) asks for a full frame
+bool full_row(const double *T, int i) { return !T || T[16 * i + 15] == 0.0; }
+
+// enqueue one frame of every stream on the lanes, forked from and joined back
+// into `s`: full range where `T` says so (host T, or NULL = every stream),
+// otherwise a steady-state frame with the ego-motion in b->Tdev; images from
+// the arrays, or the default buffers where an array is NULL
+int batch_enqueue(sgm_batch *b, const double *T, const uint8_t *const *l, const uint8_t *const *r,
+                  const int32_t *pitch, hipStream_t s)
 {
     hipError_t e = hipEventRecord(b->fork, s);
-    for (int l = 0; l < b->nlanes && e == hipSuccess; l++)
-        e = hipStreamWaitEvent(b->lane[l], b->fork, 0);
+    for (int k = 0; k < b->nlanes && e == hipSuccess; k++)
+        e = hipStreamWaitEvent(b->lane[k], b->fork, 0);
     if (e != hipSuccess)
         return hip_fail(e, "batch fork");
     for (int k = 0; k < b->n; k++) {
         const int i = b->seq[k];
         hipStream_t ls = b->lane[b->lane_of[i]];
-        int rc = full ? full_frame_impl(b->ctx[i], b->left[i], b->right[i], b->pitch[i], ls)
-                      : reduced_frame_impl(b->ctx[i], b->left[i], b->right[i], b->pitch[i], nullptr,
-                                           b->Tdev + 16 * i, ls);
-        if (rc)
-            return rc;
+        const uint8_t *li = l ? l[i] : b->left[i], *ri = r ? r[i] : b->right[i];
+        const int32_t pi = pitch ? pitch[i] : b->pitch[i];
+        int rc = full_row(T, i) ? full_frame_impl(b->ctx[i], li, ri, pi, ls)
+                                : reduced_frame_impl(b->ctx[i], li, ri, pi, nullptr, b->Tdev + 16 * i, ls);
+        if (rc) {
+            char msg[sizeof(g_err)];
+            snprintf(msg, sizeof(msg), "%s", g_err);
+            return fail(rc, "stream %d: %s", i, msg);
+        }
     }
-    for (int l = 0; l < b->nlanes; l++) {
-        e = hipEventRecord(b->join[l], b->lane[l]);
+    for (int k = 0; k < b->nlanes; k++) {
+        e = hipEventRecord(b->join[k], b->lane[k]);
         if (e == hipSuccess)
-            e = hipStreamWaitEvent(s, b->join[l], 0);
+            e = hipStreamWaitEvent(s, b->join[k], 0);
         if (e != hipSuccess)
             return hip_fail(e, "batch join");
     }
@@ -967,11 +983,140 @@ int batch_enqueue(sgm_batch *b, bool full, hipStream_t s)
 
 int batch_upload_T(sgm_batch *b, const double *T, hipStream_t s)
 {
-    for (int i = 0; i < 16 * b->n; i++)
-        if (!isfinite(T[i]))
-            return fail(SGM_EINVAL, "T[%d] is not finite", i);
+    for (int i = 0; i < b->n; i++) {
+        if (full_row(T, i))
+            continue;
+        for (int j = 0; j < 16; j++)
+            if (!isfinite(T[16 * i + j]))
+                return fail(SGM_EINVAL, "T[%d] is not finite", 16 * i + j);
+        if (!b->ctx[i]->started)
+            return fail(SGM_ESTATE, "stream %d: steady-state frame before any full-range frame", i);
+    }
     hipError_t e = hipMemcpyAsync(b->Tdev, T, sizeof(double) * 16 * b->n, hipMemcpyHostToDevice, s);
-    return e == hipSuccess ? SGM_OK : hip_fail(e, "ego-motion upload");
+    if (e != hipSuccess)
+        return hip_fail(e, "ego-motion upload");
+    b->have_T = true;
+    return SGM_OK;
+}
+
+int batch_state_copy(sgm_batch *b, bool save, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < b->n && e == hipSuccess; i++) {
+        const size_t N = b->save_off[i + 1] - b->save_off[i], o = b->save_off[i];
+        DevBuffers &c = b->ctx[i]->b;
+        void *dst[5] = {b->save_d + o, b->save_p + o, b->save_f + o, b->save_m + o, b->save_nu + o};
+        void *src[5] = {c.d, c.p, c.sflags, c.mask, c.nu};
+        const size_t sz[5] = {N * 8, N * 8, N, N, N * 8};
+        for (int k = 0; k < 5 && e == hipSuccess; k++)
+            e = save ? hipMemcpyAsync(dst[k], src[k], sz[k], hipMemcpyDeviceToDevice, s)
+                     : hipMemcpyAsync(src[k], dst[k], sz[k], hipMemcpyDeviceToDevice, s);
+    }
+    return e == hipSuccess ? SGM_OK : hip_fail(e, save ? "state save" : "state restore");
+}
+
+// Times steady-state steps (default images, the ego-motions in b->Tdev) for
+// every schedule candidate, restoring every stream's state before each trial;
+// keeps the fastest and restores the state at the end.  reps > 0: that many
+// timed steps per candidate; reps == 0: as many as fit about budget_ms.
+int batch_autotune(sgm_batch *b, int reps, int budget_ms, int32_t *chosen, hipStream_t s)
+{
+    int rc = batch_state_copy(b, true, s);
+    if (rc)
+        return rc;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+        if (t0)
+            (void)hipEventDestroy(t0);
+        return fail(SGM_EHIP, "event creation failed");
+    }
+    struct Cand {
+        int lanes, order, hseg, halt;
+    };
+    Cand cand[64];
+    int nc = 0;
+    const int lane_opts[] = {1, 2, 4, 8, 16};
+    const int hs_opts[][2] = {{72, 0}, {48, 0}, {96, 0}, {128, 0}, {72, 1}};
+    for (int oi = 0; oi < 2; oi++)
+        for (int li = 0; li < 5; li++) {
+            if (lane_opts[li] > b->n && lane_opts[li] != 1)
+                continue;
+            for (int hi = 0; hi < 5; hi++)
+                cand[nc++] = Cand{lane_opts[li], oi, hs_opts[hi][0], hs_opts[hi][1]};
+        }
+    const Cand keep{b->nlanes, b->order, b->hseg, b->halt};
+    float best = 1e30f;
+    Cand bestc = keep;
+    int r_each = reps;
+    for (int c = 0; c < nc && !rc; c++) {
+        b->nlanes = cand[c].lanes;
+        b->order = cand[c].order;
+        b->hseg = cand[c].hseg;
+        b->halt = cand[c].halt;
+        batch_schedule(b);
+        const int nr = r_each > 0 ? r_each : 1;
+        if ((rc = batch_state_copy(b, false, s)))
+            break;
+        double Tone[16] = {0};
+        Tone[15] = 1.0;
+        double *Tall = new (std::nothrow) double[16 * (size_t)b->n];
+        if (!Tall) {
+            rc = fail(SGM_ENOMEM, "host allocation failed");
+            break;
+        }
+        for (int i = 0; i < b->n; i++)
+            memcpy(Tall + 16 * i, Tone, sizeof(Tone));
+        // every candidate starts from the saved state: warm-up, then the timed steps
+        rc = batch_enqueue(b, Tall, nullptr, nullptr, nullptr, s);   // (the kernels read b->Tdev)
+        (void)hipEventRecord(t0, s);
+        for (int r = 0; r < nr && !rc; r++)
+            rc = batch_enqueue(b, Tall, nullptr, nullptr, nullptr, s);
+        (void)hipEventRecord(t1, s);
+        delete[] Tall;
+        if (rc)
+            break;
+        if (hipEventSynchronize(t1) != hipSuccess) {
+            rc = fail(SGM_EHIP, "autotune timing failed");
+            break;
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        ms /= (float)nr;
+        if (r_each == 0) {
+            // budget: the first candidate's step time sets the repetitions of all
+            const double per = (double)ms * nc;
+            r_each = per > 0 ? (int)fmin(fmax((double)budget_ms / per, 1.0), 20.0) : 1;
+            if (r_each > 1) {
+                c--;   // time the first candidate again with the budgeted repetitions
+                continue;
+            }
+        }
+        if (ms < best) {
+            best = ms;
+            bestc = cand[c];
+        }
+    }
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    b->nlanes = rc ? keep.lanes : bestc.lanes;
+    b->order = rc ? keep.order : bestc.order;
+    b->hseg = rc ? keep.hseg : bestc.hseg;
+    b->halt = rc ? keep.halt : bestc.halt;
+    batch_schedule(b);
+    int rc2 = batch_state_copy(b, false, s);
+    if (rc)
+        return rc;
+    if (rc2)
+        return rc2;
+    if (hipStreamSynchronize(s) != hipSuccess)
+        return fail(SGM_EHIP, "autotune synchronisation failed");
+    if (chosen) {
+        chosen[0] = b->nlanes;
+        chosen[1] = b->order;
+        chosen[2] = b->hseg;
+        chosen[3] = b->halt;
+    }
+    return SGM_OK;
 }
 
 void batch_free(sgm_batch *b)
@@ -986,6 +1131,8 @@ void batch_free(sgm_batch *b)
         if (b->join[l])
             (void)hipEventDestroy(b->join[l]);
     }
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
     if (b->fork)
         (void)hipEventDestroy(b->fork);
     for (void *p : {(void *)b->Tdev, (void *)b->save_d, (void *)b->save_p, (void *)b->save_f, (void *)b->save_m,
@@ -1000,6 +1147,16 @@ void batch_free(sgm_batch *b)
     delete[] b->seq;
     delete[] b->save_off;
     delete b;
+}
+
+int check_batch(sgm_batch *b)
+{
+    if (!b)
+        return fail(SGM_EINVAL, "batch is NULL");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device)
+        return fail(SGM_EINVAL, "batch was created on device %d but device %d is current", b->device, dev);
+    return SGM_OK;
 }
 
 }  // namespace
@@ -1069,6 +1226,8 @@ int sgm_batch_create(int32_t n, const sgm_params *params, const uint8_t *const *
             e = hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming);
     }
     if (e == hipSuccess)
+        e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
         e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
     if (e != hipSuccess) {
         batch_free(b);
@@ -1108,123 +1267,70 @@ int sgm_batch_set_schedule(sgm_batch *b, int32_t lanes, int32_t order)
     return SGM_OK;
 }
 
-int sgm_batch_full(sgm_batch *b, void *stream)
+int sgm_batch_step(sgm_batch *b, const uint8_t *const *left, const uint8_t *const *right, const int32_t *pitch,
+                   const double *T, void *stream)
 {
-    if (!b)
-        return fail(SGM_EINVAL, "batch is NULL");
-    int rc = batch_enqueue(b, true, as_stream(stream));
+    int rc = check_batch(b);
     if (rc)
         return rc;
-    b->started = true;
-    return SGM_OK;
+    for (int i = 0; i < b->n; i++) {
+        if ((left && !left[i]) || (right && !right[i]))
+            return fail(SGM_EINVAL, "stream %d: NULL image", i);
+        if (pitch && pitch[i] < b->ctx[i]->g.W)
+            return fail(SGM_EINVAL, "stream %d: pitch %d < width %d", i, pitch[i], b->ctx[i]->g.W);
+    }
+    hipStream_t s = as_stream(stream);
+    if (T && (rc = batch_upload_T(b, T, s)))
+        return rc;
+    return batch_enqueue(b, T, left, right, pitch, s);
 }
 
-int sgm_batch_step(sgm_batch *b, const double *T, void *stream)
+int sgm_batch_full(sgm_batch *b, void *stream)
 {
-    if (!b || !T)
-        return fail(SGM_EINVAL, "batch or T is NULL");
-    if (!b->started)
-        return fail(SGM_ESTATE, "batch step before sgm_batch_full");
-    hipStream_t s = as_stream(stream);
-    int rc = batch_upload_T(b, T, s);
-    return rc ? rc : batch_enqueue(b, false, s);
+    return sgm_batch_step(b, nullptr, nullptr, nullptr, nullptr, stream);
 }
 
 int sgm_batch_step_graph(sgm_batch *b, const double *T, void *stream)
 {
     (void)T;
     (void)stream;
-    if (!b)
-        return fail(SGM_EINVAL, "batch is NULL");
-    return fail(SGM_EINVAL, "captured-graph stepping is disabled: its first run crashed the host process during "
-                            "stream capture and the cause has not been shown; use sgm_batch_step");
+    int rc = check_batch(b);
+    if (rc)
+        return rc;
+    return fail(SGM_EINVAL, "captured-graph stepping is disabled: capturing a batch step (streams forked onto "
+                            "lanes and side streams with events) crashed the host process inside "
+                            "hipStreamEndCapture, and the cause has not been shown; use sgm_batch_step");
 }
 
 int sgm_batch_autotune(sgm_batch *b, const double *T, int32_t reps, int32_t *chosen, void *stream)
 {
-    if (!b || !T || reps < 1)
-        return fail(SGM_EINVAL, "batch, T or reps invalid");
-    if (!b->started)
-        return fail(SGM_ESTATE, "autotune before sgm_batch_full");
-    hipStream_t s = as_stream(stream);
-    // the trial steps advance the filters: save every stream's state first
-    hipError_t e = hipSuccess;
-    for (int i = 0; i < b->n && e == hipSuccess; i++) {
-        const size_t N = b->save_off[i + 1] - b->save_off[i];
-        e = hipMemcpyAsync(b->save_d + b->save_off[i], b->ctx[i]->b.d, N * 8, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->save_p + b->save_off[i], b->ctx[i]->b.p, N * 8, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->save_f + b->save_off[i], b->ctx[i]->b.sflags, N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->save_m + b->save_off[i], b->ctx[i]->b.mask, N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->save_nu + b->save_off[i], b->ctx[i]->b.nu, N * 8, hipMemcpyDeviceToDevice, s);
-    }
-    if (e != hipSuccess)
-        return hip_fail(e, "state save");
-    hipEvent_t t0, t1;
-    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess)
-        return fail(SGM_EHIP, "event creation failed");
-    int rc = batch_upload_T(b, T, s);
-    float best = 1e30f;
-    int best_l = b->nlanes, best_o = b->order;
-    const int lane_opts[] = {1, 2, 4, 8, 16};
-    for (int oi = 0; oi < 2 && !rc; oi++) {
-        for (int li = 0; li < 5 && !rc; li++) {
-            const int l = lane_opts[li];
-            if (l > b->n && l != 1)
-                continue;
-            b->nlanes = l;
-            b->order = oi;
-            batch_schedule(b);
-            if ((rc = batch_enqueue(b, false, s)))   // warm-up
-                break;
-            (void)hipEventRecord(t0, s);
-            for (int r = 0; r < reps && !rc; r++)
-                rc = batch_enqueue(b, false, s);
-            (void)hipEventRecord(t1, s);
-            if (rc)
-                break;
-            if (hipEventSynchronize(t1) != hipSuccess) {
-                rc = fail(SGM_EHIP, "autotune timing failed");
-                break;
-            }
-            float ms = 0.f;
-            (void)hipEventElapsedTime(&ms, t0, t1);
-            if (ms < best) {
-                best = ms;
-                best_l = l;
-                best_o = oi;
-            }
-        }
-    }
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    b->nlanes = best_l;
-    b->order = best_o;
-    batch_schedule(b);
-    for (int i = 0; i < b->n && e == hipSuccess; i++) {
-        const size_t N = b->save_off[i + 1] - b->save_off[i];
-        e = hipMemcpyAsync(b->ctx[i]->b.d, b->save_d + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->ctx[i]->b.p, b->save_p + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->ctx[i]->b.sflags, b->save_f + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->ctx[i]->b.mask, b->save_m + b->save_off[i], N, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->ctx[i]->b.nu, b->save_nu + b->save_off[i], N * 8, hipMemcpyDeviceToDevice, s);
-    }
-    if (e != hipSuccess)
-        return hip_fail(e, "state restore");
+    int rc = check_batch(b);
     if (rc)
         return rc;
-    if (chosen) {
-        chosen[0] = best_l;
-        chosen[1] = best_o;
-    }
-    return SGM_OK;
+    if (!T || reps < 1)
+        return fail(SGM_EINVAL, "T is NULL or reps < 1");
+    for (int i = 0; i < b->n; i++)
+        if (full_row(T, i))
+            return fail(SGM_EINVAL, "stream %d: autotuning times steady-state frames", i);
+    hipStream_t s = as_stream(stream);
+    if ((rc = batch_upload_T(b, T, s)))
+        return rc;
+    return batch_autotune(b, reps, 0, chosen, s);
+}
+
+int sgm_autotune(sgm_batch *b, int32_t budget_ms)
+{
+    int rc = check_batch(b);
+    if (rc)
+        return rc;
+    if (budget_ms < 1)
+        return fail(SGM_EINVAL, "budget_ms must be >= 1");
+    if (!b->have_T)
+        return fail(SGM_ESTATE, "autotuning needs the ego-motions of a previous steady-state step");
+    // the batch's own stream: ordered after the caller's work by the device-wide sync below
+    if (hipDeviceSynchronize() != hipSuccess)
+        return fail(SGM_EHIP, "synchronisation failed");
+    return batch_autotune(b, 0, budget_ms, nullptr, b->cap);
 }
 
 }  // extern "C"
