@@ -1086,10 +1086,16 @@ __global__ __launch_bounds__(AV_T) void k_agg_v(AggArgs a)
 // Staging as in k_agg_v (NG chains per block, 8-row batches of right census
 // and pixel metadata in LDS, here in one buffer), but each chain (a group of
 // G lanes) keeps the previous pixel's L_r in LDS, indexed by absolute
-// disparity, and reads its d-1, d, d+1 terms back masked by that pixel's
-// window.  A step covers the window in chunks of G consecutive disparities
-// from its lower bound; the chunk loop runs to the largest count among the
-// wave's chains, so a narrow step costs one chunk.
+// disparity (slot d + 4, two buffers by step parity), and reads its d-1, d,
+// d+1 terms back masked by that pixel's window.  A step first covers the
+// disparities lo .. lo + G - 1 of its window, one per lane, which is the whole
+// of a narrow window.  The rest of a wider window (full range, wide learned
+// windows) is covered in quads: lane i of a group computes the four
+// disparities 4m .. 4m + 3 of quad m, G quads per round from the quad holding
+// lo + G, so a full-range step at D = 128 takes one narrow pass and two
+// rounds (16 lanes) or one (32 lanes) instead of eight or four passes.  A
+// quad's six predecessor terms and its four results are then aligned LDS
+// words.  The rounds run to the largest count among the wave's chains.
 
 // max of a group-uniform value over the groups of G lanes of a wave
 template <int G>
@@ -1099,13 +1105,19 @@ __device__ __forceinline__ int group_max(int v)
         return wave_max4(v);
     return max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 32));
 }
-constexpr int AV2_PAD = 18;   // state slots past D (idle lanes are clamped to D), plus d+1
+constexpr int AV2_OFF = 4;   // state slot of disparity d is d + 4 (quads start on 8-byte words)
 
-__host__ __device__ constexpr int agg_v2_spad(int D) { return (D + AV2_PAD + 1) & ~1; }
+// slots per chain: idle lanes clamp to disparity (D + 3) & ~3 and read up to
+// five past it; a multiple of four, so that every chain's buffer is 8-byte aligned
+__host__ __device__ constexpr int agg_v2_spad(int D) { return (D + 3 + 6 + AV2_OFF + 3) & ~3; }
+
+// staged census entries kept in front of the first row: a quad's dead cells
+// past the window read up to 7 entries below a row's start
+constexpr int AV2_CPAD = 8;
 
 __host__ __device__ constexpr size_t agg_v2_lds(int D, int NG, int B)
 {
-    return (size_t)B * (NG + D - 1) * 8 + (size_t)B * NG * sizeof(MetaEntry) +
+    return (size_t)(AV2_CPAD + B * (NG + D - 1)) * 8 + (size_t)B * NG * sizeof(MetaEntry) +
            (size_t)2 * NG * agg_v2_spad(D) * sizeof(uint16_t);
 }
 
@@ -1121,10 +1133,9 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
     const int span = AV_NG + D - 1;
     const int spad = agg_v2_spad(D);
     // one staging buffer: a batch's loads wait in registers until every wave has left the previous batch
-    uint64_t *cbuf = (uint64_t *)smem;                                            // [B][span]
-    MetaEntry *mbuf = (MetaEntry *)(smem + (size_t)AV_B * span * 8);              // [B][NG]
-    uint16_t *sbuf = (uint16_t *)(smem + (size_t)AV_B * span * 8 +
-                                  (size_t)AV_B * AV_NG * sizeof(MetaEntry));      // [2][NG][spad]
+    uint64_t *cbuf = (uint64_t *)smem + AV2_CPAD;                                 // [B][span]
+    MetaEntry *mbuf = (MetaEntry *)(cbuf + (size_t)AV_B * span);                  // [B][NG]
+    uint16_t *sbuf = (uint16_t *)(mbuf + (size_t)AV_B * AV_NG);                   // [2][NG][spad]
     const int k = a.slot[pi];
     const int rx = a.rx[pi], ry = a.ry[pi];
     const int kmin = a.kmin[pi];
@@ -1206,13 +1217,10 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
             // the next row's metadata is read a step ahead: its LDS latency overlaps this step
             en = mb[min(r + 1, rows - 1) * AV_NG + grp];
             const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-            // chunks of G consecutive disparities from lo
-            const int nt = act ? (hi - lo) / G + 1 : 0;
-            if (__ballot(nt > 0) == 0)
+            if (__ballot(act) == 0)
                 continue;                                  // no chain of the wave is on the image
-            // most steps fit one chunk in every chain; the count is reduced only otherwise
-            const int ntw = __ballot(nt > 1) ? group_max<G>(nt) : 1;
-            const int qb = sb0 + (cur ? sdel : 0);         // previous pixel's L_r (slot d + 1)
+            const bool wide = act && hi - lo >= G;          // cells beyond the one-per-lane pass
+            const int qb = sb0 + (cur ? sdel : 0);         // previous pixel's L_r (slot d + 4)
             const int pb = sb0 + (cur ? 0 : sdel);
             // before the first pixel every term is masked off and mq is 0
             const int cap = mq + p2;                       // the P2 term
@@ -1220,30 +1228,94 @@ __device__ __forceinline__ void agg_v2_chains(const AggArgs &a, const int pi)
             const uint64_t *crow = cb + (size_t)r * span;
             const int cbase = grp + D - 1;                 // the chain's column in the staged span
             int rmin = LBIG;
-            auto chunk = [&](int j, bool live) {
-                const int d = lo + G * j + lane;
-                const int dd = min(d, D);                  // keeps idle lanes inside the chain's slots
-                // unconditional reads; out-of-window terms become LBIG (absent)
-                const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
-                const uint64_t crv = crow[max(cbase - dd, 0)];
-                const uint32_t tq = (uint32_t)(dd - loq);
-                const int a0 = tq <= spanq ? v0 : LBIG;
-                const int am = tq - 1u <= spanq ? vm : LBIG;
-                const int ap = tq + 1u <= spanq ? vp : LBIG;
-                // branch-free: the terms are read for every lane and masked
+            // the one-per-lane pass over lo .. lo + G - 1: reads, then results
+            const int dn = min(lo + lane, D);              // keeps idle lanes inside the chain's slots
+            const bool nlive = act && lo + lane <= hi;
+            // unconditional reads; out-of-window terms become LBIG (absent)
+            const int nv0 = sbuf[qb + dn + AV2_OFF], nvm = sbuf[qb + dn + AV2_OFF - 1],
+                      nvp = sbuf[qb + dn + AV2_OFF + 1];
+            const uint64_t ncr = crow[max(cbase - dn, 0)];
+            auto narrow = [&]() {
+                const uint32_t tq = (uint32_t)(dn - loq);
+                const int a0 = tq <= spanq ? nv0 : LBIG;
+                const int am = tq - 1u <= spanq ? nvm : LBIG;
+                const int ap = tq + 1u <= spanq ? nvp : LBIG;
                 const int best = min(min(a0, cap), min(am, ap) + p1) & started;
-                const int pc = __popcll(e.cl ^ crv);
-                const int c = dd > x ? nbits : pc;
-                const int L = live ? c + best - mq : LBIG;
+                const int pc = __popcll(e.cl ^ ncr);
+                const int c = dn > x ? nbits : pc;
+                const int L = nlive ? c + best - mq : LBIG;
                 // idle lanes write LBIG into slots outside the window (masked when read)
-                sbuf[pb + dd + 1] = (uint16_t)L;
-                if (live)
-                    lrk[e.off + (uint32_t)(dd - lo)] = (uint8_t)L;
+                sbuf[pb + dn + AV2_OFF] = (uint16_t)L;
+                if (nlive)
+                    lrk[e.off + (uint32_t)(dn - lo)] = (uint8_t)L;
                 rmin = min(rmin, L);
             };
-            chunk(0, act && lo + lane <= hi);
-            for (int j = 1; j < ntw; j++)
-                chunk(j, j < nt && lo + G * j + lane <= hi);
+            // a quad: four disparities dq .. dq + 3 (dq a multiple of 4) of a wide window
+            struct QuadIn {
+                int dq;
+                uint32_t wlo, whi;
+                uint2 wmid;
+                uint64_t cr[4];
+            };
+            auto quad_load = [&](int d0) {
+                QuadIn qi;
+                qi.dq = min(d0, (D + 3) & ~3);             // idle lanes stay inside the chain's slots
+                // predecessor terms of dq - 1 .. dq + 4 from three aligned words
+                const uint16_t *qs = sbuf + qb + qi.dq + AV2_OFF;
+                qi.wlo = *(const uint32_t *)(qs - 2);
+                qi.wmid = *(const uint2 *)qs;
+                qi.whi = *(const uint32_t *)(qs + 4);
+                // right census of columns x - dq - 3 .. x - dq (the index is >= -7,
+                // inside the front entries, and below 0 for dead cells only)
+                const uint64_t *cp = crow + (cbase - qi.dq - 3);
+#pragma unroll
+                for (int j = 0; j < 4; j++)
+                    qi.cr[j] = cp[3 - j];
+                return qi;
+            };
+            auto quad = [&](const QuadIn &qi) {
+                const int dq = qi.dq;
+                int pv[6] = {(int)(qi.wlo >> 16), (int)(qi.wmid.x & 0xFFFFu), (int)(qi.wmid.x >> 16),
+                             (int)(qi.wmid.y & 0xFFFFu), (int)(qi.wmid.y >> 16), (int)(qi.whi & 0xFFFFu)};
+                const uint32_t tq0 = (uint32_t)(dq - 1 - loq);
+#pragma unroll
+                for (int i = 0; i < 6; i++)
+                    pv[i] = tq0 + (uint32_t)i <= spanq ? pv[i] : LBIG;
+                int L4[4];
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int d = dq + j;
+                    const int best = min(min(pv[j + 1], cap), min(pv[j], pv[j + 2]) + p1) & started;
+                    const int c = d > x ? nbits : (int)__popcll(e.cl ^ qi.cr[j]);
+                    L4[j] = wide && d <= hi ? c + best - mq : LBIG;
+                    rmin = min(rmin, L4[j]);
+                }
+                if (wide) {
+                    // slots above hi lie outside the window (masked when read)
+                    uint2 wv;
+                    wv.x = (uint32_t)L4[0] | ((uint32_t)L4[1] << 16);
+                    wv.y = (uint32_t)L4[2] | ((uint32_t)L4[3] << 16);
+                    *(uint2 *)(sbuf + pb + dq + AV2_OFF) = wv;
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        if (dq + j <= hi)
+                            lrk[e.off + (uint32_t)(dq + j - lo)] = (uint8_t)L4[j];
+                }
+            };
+            if (__ballot(wide)) {
+                // quads from the one holding lo + G (cells below lo + G are recomputed
+                // alike); the first round's reads go out beside the narrow pass's
+                const int q0 = (lo + G) & ~3;
+                const int nq = wide ? (hi - q0) / (4 * G) + 1 : 0;
+                const int nqw = group_max<G>(nq);
+                const QuadIn q1 = quad_load(q0 + 4 * lane);
+                narrow();
+                quad(q1);
+                for (int j = 1; j < nqw; j++)
+                    quad(quad_load(q0 + 4 * (G * j + lane)));
+            } else {
+                narrow();
+            }
             const int m = group_min<G>(rmin);
             if (act) {
                 mq = m;
@@ -1466,7 +1538,7 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const int d = (lo / G) * G + G * j + lane;
                 if (j < nt && d >= lo && d <= hi) {
                     const int v = lrk[off + (uint32_t)(d - lo)];
-                    sbuf[qb + d + 1] = (uint16_t)v;
+                    sbuf[qb + d + AV2_OFF] = (uint16_t)v;
                     rmin = min(rmin, v);
                 }
             }
@@ -1504,12 +1576,9 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 // the next step's metadata is read a step ahead: its LDS latency overlaps this step
                 en = mb[min(r + 1, rows - 1) * NC + cg];
                 const int lo = (int)(e.win & 255), hi = lo + (int)(e.win >> 8);
-                // chunks of G consecutive disparities from lo
-                const int nt = act ? (hi - lo) / G + 1 : 0;
-                if (__ballot(nt > 0) == 0)
+                if (__ballot(act) == 0)
                     continue;                                  // no group of the wave is working
-                // most steps fit one chunk in every group; the count is reduced only otherwise
-                const int ntw = __ballot(nt > 1) ? group_max<G>(nt) : 1;
+                const bool wide = act && hi - lo >= G;          // cells beyond the one-per-lane pass
                 const int qb = sb0 + (cur ? sdel : 0);
                 const int pb = sb0 + (cur ? 0 : sdel);
                 // before the first pixel every term is masked off and mq is 0
@@ -1517,29 +1586,16 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                 const uint32_t spanq = (uint32_t)(hiq - loq);   // previous window (used once started)
                 int rmin = LBIG;
                 bool diff = false;
-                auto chunk = [&](int j, bool live) {
-                    const int d = lo + G * j + lane;
-                    const int dd = min(d, D);
-                    const int v0 = sbuf[qb + dd + 1], vm = sbuf[qb + dd], vp = sbuf[qb + dd + 2];
-                    const uint64_t crv = crow[(x - dd) & (R - 1)];   // right census at column x - d
-                    const uint32_t tq = (uint32_t)(dd - loq);
-                    const int a0 = tq <= spanq ? v0 : LBIG;
-                    const int am = tq - 1u <= spanq ? vm : LBIG;
-                    const int ap = tq + 1u <= spanq ? vp : LBIG;
-                    // branch-free: the terms are read for every lane and masked
-                    const int best = min(min(a0, cap), min(am, ap) + p1) & started;
-                    const int pc = __popcll(e.cl ^ crv);
-                    const int c = dd > x ? nbits : pc;
-                    const int L = live ? c + best - mq : LBIG;
+                // one result: compare (HS_FIX: with the other trajectory; HS_SEQ:
+                // with the stored loss) and store (trajectory A)
+                auto emit = [&](int d, int L, bool live) {
                     if (MODE == HS_FIX) {
                         // lane i of trajectory A sits G lanes below lane i of B
                         const int other = __shfl_xor(L, G, 64);
                         diff = diff || (live && other != L);
                     }
-                    // idle lanes write LBIG into slots outside the window (masked when read)
-                    sbuf[pb + dd + 1] = (uint16_t)L;
                     if (live) {
-                        uint8_t *dst = lrk + e.off + (uint32_t)(dd - lo);
+                        uint8_t *dst = lrk + e.off + (uint32_t)(d - lo);
                         if (MODE == HS_SEQ)
                             diff = diff || (*dst != (uint8_t)L);
                         if (traj_a)
@@ -1547,9 +1603,87 @@ __global__ __launch_bounds__(AH2_T) void k_agg_h2(AggArgs a, int seg, int nseg)
                     }
                     rmin = min(rmin, L);
                 };
-                chunk(0, act && lo + lane <= hi);
-                for (int j = 1; j < ntw; j++)
-                    chunk(j, j < nt && lo + G * j + lane <= hi);
+                // the one-per-lane pass over lo .. lo + G - 1: reads, then results
+                const int dn = min(lo + lane, D);              // keeps idle lanes inside the group's slots
+                const bool nlive = act && lo + lane <= hi;
+                // unconditional reads; out-of-window terms become LBIG (absent)
+                const int nv0 = sbuf[qb + dn + AV2_OFF], nvm = sbuf[qb + dn + AV2_OFF - 1],
+                          nvp = sbuf[qb + dn + AV2_OFF + 1];
+                const uint64_t ncr = crow[(x - dn) & (R - 1)];  // right census at column x - d
+                auto narrow = [&]() {
+                    const uint32_t tq = (uint32_t)(dn - loq);
+                    const int a0 = tq <= spanq ? nv0 : LBIG;
+                    const int am = tq - 1u <= spanq ? nvm : LBIG;
+                    const int ap = tq + 1u <= spanq ? nvp : LBIG;
+                    const int best = min(min(a0, cap), min(am, ap) + p1) & started;
+                    const int pc = __popcll(e.cl ^ ncr);
+                    const int c = dn > x ? nbits : pc;
+                    const int L = nlive ? c + best - mq : LBIG;
+                    // idle lanes write LBIG into slots outside the window (masked when read)
+                    sbuf[pb + dn + AV2_OFF] = (uint16_t)L;
+                    emit(dn, L, nlive);
+                };
+                // a quad: four disparities dq .. dq + 3 (dq a multiple of 4) of a wide window
+                struct QuadIn {
+                    int dq;
+                    uint32_t wlo, whi;
+                    uint2 wmid;
+                    uint64_t cr[4];
+                };
+                auto quad_load = [&](int d0) {
+                    QuadIn qi;
+                    qi.dq = min(d0, (D + 3) & ~3);             // idle lanes stay inside the group's slots
+                    // predecessor terms of dq - 1 .. dq + 4 from three aligned words
+                    const uint16_t *qs = sbuf + qb + qi.dq + AV2_OFF;
+                    qi.wlo = *(const uint32_t *)(qs - 2);
+                    qi.wmid = *(const uint2 *)qs;
+                    qi.whi = *(const uint32_t *)(qs + 4);
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        qi.cr[j] = crow[(x - qi.dq - j) & (R - 1)];
+                    return qi;
+                };
+                auto quad = [&](const QuadIn &qi) {
+                    const int dq = qi.dq;
+                    int pv[6] = {(int)(qi.wlo >> 16), (int)(qi.wmid.x & 0xFFFFu), (int)(qi.wmid.x >> 16),
+                                 (int)(qi.wmid.y & 0xFFFFu), (int)(qi.wmid.y >> 16), (int)(qi.whi & 0xFFFFu)};
+                    const uint32_t tq0 = (uint32_t)(dq - 1 - loq);
+#pragma unroll
+                    for (int i = 0; i < 6; i++)
+                        pv[i] = tq0 + (uint32_t)i <= spanq ? pv[i] : LBIG;
+                    int L4[4];
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int d = dq + j;
+                        const int best = min(min(pv[j + 1], cap), min(pv[j], pv[j + 2]) + p1) & started;
+                        const int c = d > x ? nbits : (int)__popcll(e.cl ^ qi.cr[j]);
+                        L4[j] = wide && d <= hi ? c + best - mq : LBIG;
+                    }
+                    if (wide) {
+                        // slots above hi lie outside the window (masked when read)
+                        uint2 wv;
+                        wv.x = (uint32_t)L4[0] | ((uint32_t)L4[1] << 16);
+                        wv.y = (uint32_t)L4[2] | ((uint32_t)L4[3] << 16);
+                        *(uint2 *)(sbuf + pb + dq + AV2_OFF) = wv;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; j++)
+                        emit(dq + j, L4[j], wide && dq + j <= hi);
+                };
+                if (__ballot(wide)) {
+                    // quads from the one holding lo + G (cells below lo + G are recomputed
+                    // alike); the first round's reads go out beside the narrow pass's
+                    const int q0 = (lo + G) & ~3;
+                    const int nq = wide ? (hi - q0) / (4 * G) + 1 : 0;
+                    const int nqw = group_max<G>(nq);
+                    const QuadIn q1 = quad_load(q0 + 4 * lane);
+                    narrow();
+                    quad(q1);
+                    for (int j = 1; j < nqw; j++)
+                        quad(quad_load(q0 + 4 * (G * j + lane)));
+                } else {
+                    narrow();
+                }
                 const int m = group_min<G>(rmin);
                 if (act) {
                     mq = m;
