@@ -4,16 +4,19 @@
 // training (backward pass, Gaussian NLL loss, Adam) and the per-pixel glue
 // (network input, head, training targets).
 //
-// Convolutions are implicit GEMMs on the bf16 matrix cores
-// (v_mfma_f32_16x16x16_bf16, fp32 accumulation): M = 16 output pixels of a
-// row, N = output channels, K = (tap, input channel).  Activations are NHWC
-// bfloat16; weights are pre-arranged ("fragments") so that each lane of a
-// wave loads its four K values of the B operand with one 8-byte read.
+// Convolutions are implicit GEMMs on the bf16 matrix cores with fp32
+// accumulation: M = 16 output pixels of a row, N = output channels, K =
+// (tap, input channel).  Activations are NHWC bfloat16; weights are
+// pre-arranged ("fragments") so that each lane of a wave reads its K values
+// of the B operand with one load.  The forward pass runs on gfx950's
+// v_mfma_f32_16x16x32_bf16 (eight K values per lane, weights held in
+// registers for a whole tile); the backward pass keeps the 16x16x16 form.
 #include "sgm_internal.h"
 
 namespace sgmk {
 
 typedef short bf16x4 __attribute__((__vector_size__(4 * sizeof(short))));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
 
 constexpr int kCin[kCnnLayers] = {4, 16, 32, 32, 16};
@@ -47,7 +50,7 @@ __host__ __device__ constexpr int ffrag_total()
     return o;
 }
 // start of layer l's forward (bwd = false) or backward (bwd = true, l >= 1)
-// fragments; frag_off(kCnnLayers, true) is the total
+// fragments; frag_off(kCnnLayers, true) is the end of both
 __host__ __device__ constexpr int frag_off(int l, bool bwd)
 {
     int o = 0;
@@ -64,7 +67,19 @@ __host__ __device__ constexpr int frag_off(int l, bool bwd)
     return o;
 }
 
-size_t cnn_frag_count() { return (size_t)frag_off(kCnnLayers, true); }
+// forward fragments of the 16x16x32 kernel: [ksteps32][ntiles][64 lanes] x 8
+// bf16 (two u64 each), after the others (at an even u64 index: 16-byte aligned)
+__host__ __device__ constexpr int ksteps32(int cin) { return (9 * cin + 31) / 32; }
+__host__ __device__ constexpr int f2_count(int l) { return ksteps32(kCin[l]) * ntiles(kCout[l]) * 64; }
+__host__ __device__ constexpr int f2_off(int l)   // in u64
+{
+    int o = (frag_off(kCnnLayers, true) + 1) & ~1;
+    for (int i = 0; i < l; i++)
+        o += 2 * f2_count(i);
+    return o;
+}
+
+size_t cnn_frag_count() { return (size_t)f2_off(kCnnLayers); }
 
 __device__ __forceinline__ uint16_t f32_to_bf16(float f)
 {
@@ -131,10 +146,46 @@ __global__ void k_pack(const float *__restrict__ theta, uint64_t *__restrict__ f
     frag[idx] = packed;
 }
 
+// B operand of the 16x16x32 forward kernel: lane l of fragment (kk, nt)
+// holds B[k][n] for n = 16 nt + l % 16 and k = 32 kk + 8 (l / 16) + j,
+// j = 0..7, with k = tap * cin + c and B[k][n] = W[n][tap][c] (zero past the
+// last tap or output channel)
+__global__ void k_pack2(const float *__restrict__ theta, uint64_t *__restrict__ frag)
+{
+    int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    int l = 0;
+    while (l < kCnnLayers && idx >= f2_count(l))
+        idx -= f2_count(l++);
+    if (l >= kCnnLayers)
+        return;
+    const int cin = kCin[l], cout = kCout[l];
+    const float *W = theta + param_off(l);
+    const int nt_count = ntiles(cout);
+    const int lane = idx & 63;
+    const int nt = (idx >> 6) % nt_count;
+    const int kk = (idx >> 6) / nt_count;
+    const int n = nt * 16 + (lane & 15);
+    uint64_t half[2] = {0, 0};
+    for (int j = 0; j < 8; j++) {
+        const int k = kk * 32 + (lane >> 4) * 8 + j;
+        float v = 0.f;
+        if (k < 9 * cin && n < cout)
+            v = W[(n * 9 + k / cin) * cin + k % cin];
+        half[j >> 2] |= (uint64_t)f32_to_bf16(v) << (16 * (j & 3));
+    }
+    uint64_t *dst = frag + f2_off(l) + 2 * (size_t)idx;
+    dst[0] = half[0];
+    dst[1] = half[1];
+}
+
 hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s)
 {
-    const int n = (int)cnn_frag_count();
+    const int n = (int)frag_off(kCnnLayers, true);
     hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, theta, frag);
+    int n2 = 0;
+    for (int l = 0; l < kCnnLayers; l++)
+        n2 += f2_count(l);
+    hipLaunchKernelGGL(k_pack2, dim3((n2 + 255) / 256), dim3(256), 0, s, theta, frag);
     return hipGetLastError();
 }
 
@@ -247,6 +298,196 @@ static hipError_t conv(int nimg, int H, int W, const uint16_t *x, const uint64_t
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution, forward, on v_mfma_f32_16x16x32_bf16
+//
+// A block computes an 8 x 64 output tile: wave w takes rows 2w and 2w+1,
+// four M-tiles of 16 pixels per row, all N-tiles.  The input tile and its
+// one-pixel halo sit in LDS with a padded pixel stride (CIN + 8 values for
+// CIN >= 16), so that the 16-byte A reads of sixteen neighbouring pixels
+// fall in distinct banks; the layer's B fragments are read once into
+// registers.  Lane l reads, for k-step kk, the eight K values 32 kk + 8 (l/16)
+// + j: one tap and eight channels (CIN = 32), or half of one of two taps
+// (CIN = 16), or two taps of four channels (CIN = 4).  The results go
+// through LDS (bias, ReLU, bfloat16) and leave in 16-byte row stores.
+// ---------------------------------------------------------------------------
+
+constexpr int C2_TY = 8, C2_TX = 64, C2_SY = C2_TY + 2, C2_SX = C2_TX + 2;
+
+__host__ __device__ constexpr int c2_ps(int cin) { return cin >= 16 ? cin + 8 : cin; }   // LDS pixel stride
+__host__ __device__ constexpr int c2_out_bytes(int cout, int epi)
+{
+    return C2_TY * C2_TX * cout * (epi == EPI_F32 ? 4 : 2);
+}
+__host__ __device__ constexpr int c2_lds(int cin, int cout, int epi)
+{
+    const int in = C2_SY * C2_SX * c2_ps(cin) * 2;
+    const int out = c2_out_bytes(cout, epi);
+    return in > out ? in : out;
+}
+
+template <int CIN, int COUT, int EPI>
+__global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__restrict__ x,
+                                               const uint64_t *__restrict__ frag, const float *__restrict__ bias,
+                                               uint16_t *__restrict__ y, float *__restrict__ yf)
+{
+    static_assert(EPI == EPI_RELU || EPI == EPI_F32, "forward epilogues");
+    static_assert(CIN == 4 || CIN == 16 || CIN == 32, "input channels");
+    constexpr int KS = ksteps32(CIN), NT = ntiles(COUT), PS = c2_ps(CIN);
+    constexpr int MW = 2 * (C2_TX / 16);   // M-tiles per wave
+    __shared__ __align__(16) uint16_t smem[c2_lds(CIN, COUT, EPI) / 2];
+    const int img = blockIdx.z;
+    const int y0 = blockIdx.y * C2_TY, x0 = blockIdx.x * C2_TX;
+    const size_t ibase = (size_t)img * H * W;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kg = lane >> 4, col = lane & 15;
+    // this lane's B fragments for the whole layer
+    uint4 bfr[KS][NT];
+    {
+        const uint4 *fb = (const uint4 *)frag;
+#pragma unroll
+        for (int kk = 0; kk < KS; kk++)
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                bfr[kk][t] = fb[(kk * NT + t) * 64 + lane];
+    }
+    // stage the input tile with its halo (zeros outside the image)
+    {
+        constexpr int CH = CIN >= 8 ? 8 : 4;              // channels per staged chunk
+        constexpr int NCH = C2_SY * C2_SX * (CIN / CH);
+        constexpr int PER = (NCH + 255) / 256;
+        if (CH == 8) {
+            uint4 v[PER];
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                const int q = e % (CIN / CH), px = e / (CIN / CH);
+                const int sy = px / C2_SX, sx = px - sy * C2_SX;
+                const int gy = y0 + sy - 1, gx = x0 + sx - 1;
+                const bool ok = e < NCH && gy >= 0 && gy < H && gx >= 0 && gx < W;
+                const size_t src = ok ? (ibase + (size_t)gy * W + gx) * CIN + CH * q : 0;
+                const uint4 u = *(const uint4 *)(x + src);
+                v[i] = ok ? u : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                const int q = e % (CIN / CH), px = e / (CIN / CH);
+                if (e < NCH)
+                    *(uint4 *)(smem + px * PS + CH * q) = v[i];
+            }
+        } else {
+            uint2 v[PER];
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                const int sy = e / C2_SX, sx = e - sy * C2_SX;
+                const int gy = y0 + sy - 1, gx = x0 + sx - 1;
+                const bool ok = e < NCH && gy >= 0 && gy < H && gx >= 0 && gx < W;
+                const size_t src = ok ? (ibase + (size_t)gy * W + gx) * CIN : 0;
+                const uint2 u = *(const uint2 *)(x + src);
+                v[i] = ok ? u : make_uint2(0u, 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < PER; i++) {
+                const int e = threadIdx.x + 256 * i;
+                if (e < NCH)
+                    *(uint2 *)(smem + e * PS) = v[i];
+            }
+        }
+    }
+    __syncthreads();
+    f32x4 acc[MW][NT];
+#pragma unroll
+    for (int m = 0; m < MW; m++)
+#pragma unroll
+        for (int t = 0; t < NT; t++)
+            acc[m][t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kk = 0; kk < KS; kk++) {
+#pragma unroll
+        for (int m = 0; m < MW; m++) {
+            const int row = 2 * wave + m / (C2_TX / 16);          // output row in the tile
+            const int cx = (m % (C2_TX / 16)) * 16 + col;         // output column in the tile
+            uint4 av;
+            if (CIN == 32) {
+                const int ky = kk / 3, kx = kk % 3;
+                av = *(const uint4 *)(smem + ((row + ky) * C2_SX + cx + kx) * PS + 8 * kg);
+            } else if (CIN == 16) {
+                const int tap = 2 * kk + (kg >> 1);
+                const int ky = tap / 3, kx = tap % 3;
+                av = make_uint4(0u, 0u, 0u, 0u);
+                if (tap < 9)
+                    av = *(const uint4 *)(smem + ((row + ky) * C2_SX + cx + kx) * PS + 8 * (kg & 1));
+            } else {
+                const int t0 = 8 * kk + 2 * kg, t1 = t0 + 1;
+                uint2 lo = make_uint2(0u, 0u), hi = make_uint2(0u, 0u);
+                if (t0 < 9)
+                    lo = *(const uint2 *)(smem + ((row + t0 / 3) * C2_SX + cx + t0 % 3) * PS);
+                if (t1 < 9)
+                    hi = *(const uint2 *)(smem + ((row + t1 / 3) * C2_SX + cx + t1 % 3) * PS);
+                av = make_uint4(lo.x, lo.y, hi.x, hi.y);
+            }
+            const bf16x8 a = __builtin_bit_cast(bf16x8, av);
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8, bfr[kk][t]),
+                                                                    acc[m][t], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // every wave has read the input tile: its LDS takes the results
+    // D[i][n]: lane holds pixels i = 4 kg + e of its M-tile, channel n = 16 t + col
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+        const int n = t * 16 + col;
+        if (n >= COUT)
+            continue;
+        const float bv = bias[n];
+#pragma unroll
+        for (int m = 0; m < MW; m++) {
+            const int row = 2 * wave + m / (C2_TX / 16);
+            const int px0 = row * C2_TX + (m % (C2_TX / 16)) * 16 + 4 * kg;
+#pragma unroll
+            for (int e = 0; e < 4; e++) {
+                const float v = acc[m][t][e] + bv;
+                if (EPI == EPI_RELU)
+                    smem[(px0 + e) * COUT + n] = f32_to_bf16(fmaxf(v, 0.f));
+                else
+                    ((float *)smem)[(px0 + e) * COUT + n] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // rows of the tile to memory in 16-byte (8-byte for the fp32 head) pieces
+    constexpr int PB = COUT * (EPI == EPI_F32 ? 4 : 2);   // bytes per pixel
+    constexpr int CB = PB >= 16 ? 16 : PB;                 // bytes per piece
+    constexpr int PPR = C2_TX * PB / CB;                   // pieces per tile row
+    const int nx = min(C2_TX, W - x0);
+    for (int e = threadIdx.x; e < C2_TY * PPR; e += 256) {
+        const int r = e / PPR, c = e - r * PPR;
+        const int gy = y0 + r;
+        const int px = c * CB / PB;                        // pixel of the piece in its row
+        if (gy >= H || px >= nx)
+            continue;
+        const uint8_t *src = (const uint8_t *)smem + (size_t)r * C2_TX * PB + (size_t)c * CB;
+        uint8_t *dst = (EPI == EPI_F32 ? (uint8_t *)yf : (uint8_t *)y) +
+                       ((ibase + (size_t)gy * W + x0) * PB + (size_t)c * CB);
+        if (CB == 16)
+            *(uint4 *)dst = *(const uint4 *)src;
+        else
+            *(uint2 *)dst = *(const uint2 *)src;
+    }
+}
+
+template <int CIN, int COUT, int EPI>
+static hipError_t conv2(int nimg, int H, int W, const uint16_t *x, const uint64_t *frag, const float *bias,
+                        uint16_t *y, float *yf, hipStream_t s)
+{
+    dim3 grd((W + C2_TX - 1) / C2_TX, (H + C2_TY - 1) / C2_TY, nimg);
+    hipLaunchKernelGGL((k_conv2<CIN, COUT, EPI>), grd, dim3(256), 0, s, H, W, x, frag, bias, y, yf);
+    return hipGetLastError();
+}
+
 hipError_t cnn_forward(const float *theta, const uint64_t *frag, const uint16_t *x, int nimg, int H, int W,
                        uint16_t *a1, uint16_t *a2, uint16_t *a3, uint16_t *a4, float *out, hipStream_t s)
 {
@@ -256,16 +497,16 @@ hipError_t cnn_forward(const float *theta, const uint64_t *frag, const uint16_t 
         if ((e = (call)) != hipSuccess) \
             return e;                 \
     } while (0)
-    CNN_TRY((conv<4, 16, EPI_RELU>(nimg, H, W, x, frag + frag_off(0, false), theta + param_off(0) + 9 * 4 * 16,
-                                   nullptr, a1, nullptr, s)));
-    CNN_TRY((conv<16, 32, EPI_RELU>(nimg, H, W, a1, frag + frag_off(1, false),
-                                    theta + param_off(1) + 9 * 16 * 32, nullptr, a2, nullptr, s)));
-    CNN_TRY((conv<32, 32, EPI_RELU>(nimg, H, W, a2, frag + frag_off(2, false),
-                                    theta + param_off(2) + 9 * 32 * 32, nullptr, a3, nullptr, s)));
-    CNN_TRY((conv<32, 16, EPI_RELU>(nimg, H, W, a3, frag + frag_off(3, false),
-                                    theta + param_off(3) + 9 * 32 * 16, nullptr, a4, nullptr, s)));
-    CNN_TRY((conv<16, 2, EPI_F32>(nimg, H, W, a4, frag + frag_off(4, false), theta + param_off(4) + 9 * 16 * 2,
-                                  nullptr, nullptr, out, s)));
+    CNN_TRY((conv2<4, 16, EPI_RELU>(nimg, H, W, x, frag + f2_off(0), theta + param_off(0) + 9 * 4 * 16, a1,
+                                    nullptr, s)));
+    CNN_TRY((conv2<16, 32, EPI_RELU>(nimg, H, W, a1, frag + f2_off(1), theta + param_off(1) + 9 * 16 * 32, a2,
+                                     nullptr, s)));
+    CNN_TRY((conv2<32, 32, EPI_RELU>(nimg, H, W, a2, frag + f2_off(2), theta + param_off(2) + 9 * 32 * 32, a3,
+                                     nullptr, s)));
+    CNN_TRY((conv2<32, 16, EPI_RELU>(nimg, H, W, a3, frag + f2_off(3), theta + param_off(3) + 9 * 32 * 16, a4,
+                                     nullptr, s)));
+    CNN_TRY((conv2<16, 2, EPI_F32>(nimg, H, W, a4, frag + f2_off(4), theta + param_off(4) + 9 * 16 * 2, nullptr,
+                                   out, s)));
     return hipSuccess;
 }
 
