@@ -311,11 +311,7 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
         const Geometry &g = ctx->g;
         DevBuffers &b = ctx->b;
         mk.begin(SGM_PROF_CNN);
-        e = launch_features(g, b, left, pitch, b.feat, s);
-        if (e == hipSuccess)
-            e = cnn_forward(b.theta, b.frag, b.feat, 1, g.H, g.W, b.act_a, b.act_b, b.act_a, b.act_b, b.cnn_out, s);
-        if (e == hipSuccess)
-            e = launch_head(g, b, (float)p.k_sigma, s);
+        e = cnn_forward_frame(g, b, left, pitch, (float)p.k_sigma, s);
         mk.end(SGM_PROF_CNN);
         if (e != hipSuccess)
             return hip_fail(e, "window network launch");

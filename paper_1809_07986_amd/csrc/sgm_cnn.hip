@@ -90,6 +90,9 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f)
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// the same rounding (to nearest, ties to even) in one instruction (v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint16_t bf16_rne(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
 // bfloat16 nearest to a double, ties to even, directly from the 52-bit
 // significand (no intermediate float rounding); magnitudes below 2^-126
 // give signed zero
@@ -195,7 +198,7 @@ hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s)
 
 constexpr int CV_TY = 8, CV_TX = 32;   // output tile of a block (4 waves x 4 M-tiles of 16 px)
 
-enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2 };
+enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2, EPI_HEAD = 3 };
 
 // out[p][n] = sum_{tap, c} B[tap*CIN + c][n] * x[p + tap][c]  (zero padding)
 //  EPI_RELU: + bias, ReLU, bfloat16 out [p][COUT]
@@ -299,6 +302,73 @@ static hipError_t conv(int nimg, int H, int W, const uint16_t *x, const uint64_t
 }
 
 // ---------------------------------------------------------------------------
+// per-pixel glue of the learned window
+// ---------------------------------------------------------------------------
+
+// network input of pixel t = (x, y) of a predicted frame (four bfloat16):
+//  0: dhat / 64 (0 without prediction), 1: min(p^-, 16) / 4 (4 without),
+//  2: (|I(x+1)-I(x-1)| + |I(y+1)-I(y-1)|) / 256, neighbours clamped,
+//  3: min(|nu_w|, 8) / 4, nu_w the previous innovation of the warp winner
+__device__ __forceinline__ uint2 feature_px(int W, int H, int x, int y, int t, const uint8_t *left, int pitch,
+                                            const uint8_t *flags, const double *dhat, const double *pm,
+                                            const double *nu_w)
+{
+    const bool pred = flags[t] & SGM_FLAG_PRED;
+    const uint8_t *row = left + (size_t)y * pitch;
+    const int gx = abs((int)row[min(x + 1, W - 1)] - (int)row[max(x - 1, 0)]);
+    const int gy = abs((int)left[(size_t)min(y + 1, H - 1) * pitch + x] - (int)left[(size_t)max(y - 1, 0) * pitch + x]);
+    const double f0 = pred ? dhat[t] * (1.0 / 64.0) : 0.0;
+    const double f1 = pred ? fmin(pm[t], 16.0) * 0.25 : 4.0;
+    const double f2 = (double)(gx + gy) * (1.0 / 256.0);
+    const double f3 = fmin(fabs(nu_w[t]), 8.0) * 0.25;
+    const uint32_t lo = (uint32_t)f64_to_bf16(f0) | ((uint32_t)f64_to_bf16(f1) << 16);
+    const uint32_t hi = (uint32_t)f64_to_bf16(f2) | ((uint32_t)f64_to_bf16(f3) << 16);
+    return make_uint2(lo, hi);
+}
+
+// head of pixel t: network output -> half-width w = max(1, k exp(o0 / 2))
+// and measurement variance r = clamp(exp(o1), 1/16, 64) (o clipped to
+// +-30); pixels with a finite window get [floor(dhat - w), ceil(dhat + w)]
+// (double precision), or the full range when w >= 32
+__device__ __forceinline__ void head_px(int t, int D, float k_sigma, float o0, float o1, const double *dhat, float *hw,
+                                        float *rpix, uint8_t *flags, uint16_t *win)
+{
+    o0 = fminf(fmaxf(o0, -30.f), 30.f);
+    o1 = fminf(fmaxf(o1, -30.f), 30.f);
+    const float w = fmaxf(1.f, k_sigma * expf(0.5f * o0));
+    const float r = fminf(fmaxf(expf(o1), 1.f / 16.f), 64.f);
+    hw[t] = w;
+    rpix[t] = r;
+    const uint8_t fl = flags[t];
+    if (fl & SGM_FLAG_FULLWIN)
+        return;
+    if (!(w < (float)SGM_LEARNED_WMAX)) {
+        flags[t] = fl | SGM_FLAG_FULLWIN;
+        win[t] = (uint16_t)((D - 1) << 8);
+        return;
+    }
+    const double dv = dhat[t];
+    int l = (int)floor(dv - (double)w), h = (int)ceil(dv + (double)w);
+    l = l < 0 ? 0 : l;
+    h = h > D - 1 ? D - 1 : h;
+    win[t] = (uint16_t)(l | ((h - l) << 8));
+}
+
+// a frame's network: the first layer computes its input from the frame
+// (and writes it out for the tile), the last applies the head
+struct NetGlue {
+    const uint8_t *left;
+    int pitch;
+    int D;
+    float k_sigma;
+    uint8_t *flags;
+    const double *dhat, *pm, *nu_w;
+    uint16_t *feat;
+    float *hw, *rpix;
+    uint16_t *win;
+};
+
+// ---------------------------------------------------------------------------
 // 3x3 convolution, forward, on v_mfma_f32_16x16x32_bf16
 //
 // A block computes an 8 x 64 output tile: wave w takes rows 2w and 2w+1,
@@ -310,6 +380,8 @@ static hipError_t conv(int nimg, int H, int W, const uint16_t *x, const uint64_t
 // + j: one tap and eight channels (CIN = 32), or half of one of two taps
 // (CIN = 16), or two taps of four channels (CIN = 4).  The results go
 // through LDS (bias, ReLU, bfloat16) and leave in 16-byte row stores.
+// In a frame, the first layer stages the network input it computes itself
+// (FEAT) and the last applies the head to its outputs (EPI_HEAD).
 // ---------------------------------------------------------------------------
 
 constexpr int C2_TY = 8, C2_TX = 64, C2_SY = C2_TY + 2, C2_SX = C2_TX + 2;
@@ -317,7 +389,7 @@ constexpr int C2_TY = 8, C2_TX = 64, C2_SY = C2_TY + 2, C2_SX = C2_TX + 2;
 __host__ __device__ constexpr int c2_ps(int cin) { return cin >= 16 ? cin + 8 : cin; }   // LDS pixel stride
 __host__ __device__ constexpr int c2_out_bytes(int cout, int epi)
 {
-    return C2_TY * C2_TX * cout * (epi == EPI_F32 ? 4 : 2);
+    return C2_TY * C2_TX * cout * (epi == EPI_RELU ? 2 : 4);
 }
 __host__ __device__ constexpr int c2_lds(int cin, int cout, int epi)
 {
@@ -326,12 +398,13 @@ __host__ __device__ constexpr int c2_lds(int cin, int cout, int epi)
     return in > out ? in : out;
 }
 
-template <int CIN, int COUT, int EPI>
+template <int CIN, int COUT, int EPI, bool FEAT>
 __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__restrict__ x,
                                                const uint64_t *__restrict__ frag, const float *__restrict__ bias,
-                                               uint16_t *__restrict__ y, float *__restrict__ yf)
+                                               uint16_t *__restrict__ y, float *__restrict__ yf, NetGlue fg)
 {
-    static_assert(EPI == EPI_RELU || EPI == EPI_F32, "forward epilogues");
+    static_assert(EPI == EPI_RELU || EPI == EPI_F32 || EPI == EPI_HEAD, "forward epilogues");
+    static_assert(!FEAT || CIN == 4, "the network input has four channels");
     static_assert(CIN == 4 || CIN == 16 || CIN == 32, "input channels");
     constexpr int KS = ksteps32(CIN), NT = ntiles(COUT), PS = c2_ps(CIN);
     constexpr int MW = 2 * (C2_TX / 16);   // M-tiles per wave
@@ -384,9 +457,20 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
                 const int sy = e / C2_SX, sx = e - sy * C2_SX;
                 const int gy = y0 + sy - 1, gx = x0 + sx - 1;
                 const bool ok = e < NCH && gy >= 0 && gy < H && gx >= 0 && gx < W;
-                const size_t src = ok ? (ibase + (size_t)gy * W + gx) * CIN : 0;
-                const uint2 u = *(const uint2 *)(x + src);
-                v[i] = ok ? u : make_uint2(0u, 0u);
+                if (FEAT) {
+                    // the frame's network input, written out for the tile's own pixels
+                    v[i] = make_uint2(0u, 0u);
+                    if (ok) {
+                        const int t = gy * W + gx;
+                        v[i] = feature_px(W, H, gx, gy, t, fg.left, fg.pitch, fg.flags, fg.dhat, fg.pm, fg.nu_w);
+                        if (sy >= 1 && sy <= C2_TY && sx >= 1 && sx <= C2_TX)
+                            *(uint2 *)(fg.feat + (size_t)t * 4) = v[i];
+                    }
+                } else {
+                    const size_t src = ok ? (ibase + (size_t)gy * W + gx) * CIN : 0;
+                    const uint2 u = *(const uint2 *)(x + src);
+                    v[i] = ok ? u : make_uint2(0u, 0u);
+                }
             }
 #pragma unroll
             for (int i = 0; i < PER; i++) {
@@ -451,13 +535,27 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
             for (int e = 0; e < 4; e++) {
                 const float v = acc[m][t][e] + bv;
                 if (EPI == EPI_RELU)
-                    smem[(px0 + e) * COUT + n] = f32_to_bf16(fmaxf(v, 0.f));
+                    smem[(px0 + e) * COUT + n] = bf16_rne(fmaxf(v, 0.f));
                 else
                     ((float *)smem)[(px0 + e) * COUT + n] = v;
             }
         }
     }
     __syncthreads();
+    if (EPI == EPI_HEAD) {
+        // raw outputs of each tile pixel, then its half-width, variance and window
+        for (int e = threadIdx.x; e < C2_TY * C2_TX; e += 256) {
+            const int r = e / C2_TX, c = e - r * C2_TX;
+            const int gy = y0 + r, gx = x0 + c;
+            if (gy >= H || gx >= W)
+                continue;
+            const int t = gy * W + gx;
+            const float o0 = ((const float *)smem)[2 * e], o1 = ((const float *)smem)[2 * e + 1];
+            *(float2 *)(yf + 2 * (ibase + (size_t)t)) = make_float2(o0, o1);
+            head_px(t, fg.D, fg.k_sigma, o0, o1, fg.dhat, fg.hw, fg.rpix, fg.flags, fg.win);
+        }
+        return;
+    }
     // rows of the tile to memory in 16-byte (8-byte for the fp32 head) pieces
     constexpr int PB = COUT * (EPI == EPI_F32 ? 4 : 2);   // bytes per pixel
     constexpr int CB = PB >= 16 ? 16 : PB;                 // bytes per piece
@@ -479,12 +577,12 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
     }
 }
 
-template <int CIN, int COUT, int EPI>
+template <int CIN, int COUT, int EPI, bool FEAT = false>
 static hipError_t conv2(int nimg, int H, int W, const uint16_t *x, const uint64_t *frag, const float *bias,
-                        uint16_t *y, float *yf, hipStream_t s)
+                        uint16_t *y, float *yf, hipStream_t s, const NetGlue &fg = NetGlue{})
 {
     dim3 grd((W + C2_TX - 1) / C2_TX, (H + C2_TY - 1) / C2_TY, nimg);
-    hipLaunchKernelGGL((k_conv2<CIN, COUT, EPI>), grd, dim3(256), 0, s, H, W, x, frag, bias, y, yf);
+    hipLaunchKernelGGL((k_conv2<CIN, COUT, EPI, FEAT>), grd, dim3(256), 0, s, H, W, x, frag, bias, y, yf, fg);
     return hipGetLastError();
 }
 
@@ -507,6 +605,27 @@ hipError_t cnn_forward(const float *theta, const uint64_t *frag, const uint16_t 
                                      nullptr, s)));
     CNN_TRY((conv2<16, 2, EPI_F32>(nimg, H, W, a4, frag + f2_off(4), theta + param_off(4) + 9 * 16 * 2, nullptr,
                                    out, s)));
+    return hipSuccess;
+}
+
+hipError_t cnn_forward_frame(const Geometry &g, DevBuffers &b, const uint8_t *left, int pitch, float k_sigma,
+                             hipStream_t s)
+{
+    hipError_t e;
+    const NetGlue fg{left, pitch, g.D, k_sigma, b.flags, b.dhat, b.pm, b.nu_w, b.feat, b.hw, b.rpix, b.win};
+    const float *theta = b.theta;
+    const uint64_t *frag = b.frag;
+    const int H = g.H, W = g.W;
+    CNN_TRY((conv2<4, 16, EPI_RELU, true>(1, H, W, nullptr, frag + f2_off(0), theta + param_off(0) + 9 * 4 * 16,
+                                          b.act_a, nullptr, s, fg)));
+    CNN_TRY((conv2<16, 32, EPI_RELU>(1, H, W, b.act_a, frag + f2_off(1), theta + param_off(1) + 9 * 16 * 32, b.act_b,
+                                     nullptr, s)));
+    CNN_TRY((conv2<32, 32, EPI_RELU>(1, H, W, b.act_b, frag + f2_off(2), theta + param_off(2) + 9 * 32 * 32, b.act_a,
+                                     nullptr, s)));
+    CNN_TRY((conv2<32, 16, EPI_RELU>(1, H, W, b.act_a, frag + f2_off(3), theta + param_off(3) + 9 * 32 * 16, b.act_b,
+                                     nullptr, s)));
+    CNN_TRY((conv2<16, 2, EPI_HEAD>(1, H, W, b.act_b, frag + f2_off(4), theta + param_off(4) + 9 * 16 * 2, nullptr,
+                                    b.cnn_out, s, fg)));
     return hipSuccess;
 }
 
@@ -792,14 +911,8 @@ hipError_t cnn_adam(float *theta, float *m, float *v, const float *g, int step, 
     return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// per-pixel glue of the learned window
-// ---------------------------------------------------------------------------
-
-// network input of a predicted frame (bfloat16 [N][4]):
-//  0: dhat / 64 (0 without prediction), 1: min(p^-, 16) / 4 (4 without),
-//  2: (|I(x+1)-I(x-1)| + |I(y+1)-I(y-1)|) / 256, neighbours clamped,
-//  3: min(|nu_w|, 8) / 4, nu_w the previous innovation of the warp winner
+// network input of every pixel (bfloat16 [N][4]; see feature_px), for
+// callers that want it on its own (a frame's network computes its own)
 __global__ void k_features(int W, int H, const uint8_t *__restrict__ left, int pitch,
                            const uint8_t *__restrict__ flags, const double *__restrict__ dhat,
                            const double *__restrict__ pm, const double *__restrict__ nu_w,
@@ -809,17 +922,7 @@ __global__ void k_features(int W, int H, const uint8_t *__restrict__ left, int p
     if (t >= W * H)
         return;
     const int y = t / W, x = t - y * W;
-    const bool pred = flags[t] & SGM_FLAG_PRED;
-    const uint8_t *row = left + (size_t)y * pitch;
-    const int gx = abs((int)row[min(x + 1, W - 1)] - (int)row[max(x - 1, 0)]);
-    const int gy = abs((int)left[(size_t)min(y + 1, H - 1) * pitch + x] - (int)left[(size_t)max(y - 1, 0) * pitch + x]);
-    const double f0 = pred ? dhat[t] * (1.0 / 64.0) : 0.0;
-    const double f1 = pred ? fmin(pm[t], 16.0) * 0.25 : 4.0;
-    const double f2 = (double)(gx + gy) * (1.0 / 256.0);
-    const double f3 = fmin(fabs(nu_w[t]), 8.0) * 0.25;
-    const uint32_t lo = (uint32_t)f64_to_bf16(f0) | ((uint32_t)f64_to_bf16(f1) << 16);
-    const uint32_t hi = (uint32_t)f64_to_bf16(f2) | ((uint32_t)f64_to_bf16(f3) << 16);
-    *(uint2 *)(feat + (size_t)t * 4) = make_uint2(lo, hi);
+    *(uint2 *)(feat + (size_t)t * 4) = feature_px(W, H, x, y, t, left, pitch, flags, dhat, pm, nu_w);
 }
 
 hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t *left, int pitch, uint16_t *feat,
@@ -827,45 +930,6 @@ hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t
 {
     hipLaunchKernelGGL(k_features, dim3((g.N + 255) / 256), dim3(256), 0, s, g.W, g.H, left, pitch, b.flags, b.dhat,
                        b.pm, b.nu_w, feat);
-    return hipGetLastError();
-}
-
-// network output -> half-width w = max(1, k exp(o0 / 2)) and measurement
-// variance r = clamp(exp(o1), 1/16, 64) (o clipped to +-30); pixels with a
-// finite window get [floor(dhat - w), ceil(dhat + w)] (double precision),
-// or the full range when w >= 32
-__global__ void k_head(int N, int D, float k_sigma, const float *__restrict__ out, const double *__restrict__ dhat,
-                       float *__restrict__ hw, float *__restrict__ rpix, uint8_t *__restrict__ flags,
-                       uint16_t *__restrict__ win)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= N)
-        return;
-    const float o0 = fminf(fmaxf(out[2 * t], -30.f), 30.f);
-    const float o1 = fminf(fmaxf(out[2 * t + 1], -30.f), 30.f);
-    const float w = fmaxf(1.f, k_sigma * expf(0.5f * o0));
-    const float r = fminf(fmaxf(expf(o1), 1.f / 16.f), 64.f);
-    hw[t] = w;
-    rpix[t] = r;
-    const uint8_t fl = flags[t];
-    if (fl & SGM_FLAG_FULLWIN)
-        return;
-    if (!(w < (float)SGM_LEARNED_WMAX)) {
-        flags[t] = fl | SGM_FLAG_FULLWIN;
-        win[t] = (uint16_t)((D - 1) << 8);
-        return;
-    }
-    const double dv = dhat[t];
-    int l = (int)floor(dv - (double)w), h = (int)ceil(dv + (double)w);
-    l = l < 0 ? 0 : l;
-    h = h > D - 1 ? D - 1 : h;
-    win[t] = (uint16_t)(l | ((h - l) << 8));
-}
-
-hipError_t launch_head(const Geometry &g, DevBuffers &b, float k_sigma, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_head, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.D, k_sigma, b.cnn_out, b.dhat,
-                       b.hw, b.rpix, b.flags, b.win);
     return hipGetLastError();
 }
 

@@ -119,7 +119,9 @@ hipError_t cnn_loss(const float *out, const float *tgt, size_t P, float *cnt, fl
 hipError_t cnn_adam(float *theta, float *m, float *v, const float *g, int step, float lr, hipStream_t s);
 hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t *left, int pitch, uint16_t *feat,
                            hipStream_t s);
-hipError_t launch_head(const Geometry &g, DevBuffers &b, float k_sigma, hipStream_t s);
+// a frame's window network: input, five layers and head (five launches)
+hipError_t cnn_forward_frame(const Geometry &g, DevBuffers &b, const uint8_t *left, int pitch, float k_sigma,
+                             hipStream_t s);
 hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, hipStream_t s);
 hipError_t launch_targets(const Geometry &g, const DevBuffers &b, const double *dz_full, const float *gt, float *tgt,
                           hipStream_t s);
