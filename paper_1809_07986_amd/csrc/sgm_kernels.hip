@@ -1803,10 +1803,10 @@ hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_
     agg_args(g, b, hv, vv, nh, nv, maxv, skip);
     if (!nh)
         return hipSuccess;
-    // Ragged windows: segmented scanlines (16 lanes per pixel, many waves)
-    // win for 64 < D <= 128; at D <= 64 one register chunk per lane and at
-    // D = 256 the wide windows favour one 64-lane wave per scanline.
-    bool segmented = !dense && g.D > 64 && g.D <= 128;
+    // Ragged windows: segmented scanlines (16 lanes per pixel at D <= 128,
+    // 32 above, many waves) win for D > 64, wide windows included now that
+    // they are taken in quads; at D <= 64 one register chunk per lane does.
+    bool segmented = !dense && g.D > 64;
     if (!dense && g.halt)
         segmented = !segmented;
     if (segmented)
