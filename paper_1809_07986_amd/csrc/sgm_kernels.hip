@@ -864,9 +864,8 @@ __global__ __launch_bounds__(64) void k_agg_h(AggArgs a, int raise_prio)
 {
     if (pass_skipped(a.skip))
         return;
-    // with ragged windows at D > 128 this is the longer of the two concurrent
-    // aggregation streams: its waves win issue arbitration (with dense
-    // windows the vertical kernel is the longer one)
+    // with ragged windows (D <= 64, or the other kernel chosen) its waves
+    // issue at the vertical kernel's priority; dense windows keep the default
     if (raise_prio)
         __builtin_amdgcn_s_setprio(1);
     constexpr int G = 64;
@@ -1345,8 +1344,8 @@ __global__ __launch_bounds__(256) void k_agg_v2(AggArgs a)
     const int pi = blockIdx.y;
     // this kernel runs beside the horizontal passes on a second stream: at
     // D <= 128 it is the longer of the two and its waves win issue
-    // arbitration; at larger D the one-wave-per-scanline horizontal kernel is
-    // the longer one and takes the priority instead
+    // arbitration; at larger D the two run at equal priority (raising either
+    // one only moves time between them)
     if (MAXD <= 128)
         __builtin_amdgcn_s_setprio(1);
     if (a.rx[pi] == 0)
