@@ -38,32 +38,15 @@ __host__ __device__ constexpr int param_off(int l)
 }
 static_assert(param_off(kCnnLayers) == SGM_CNN_NPARAMS, "parameter count");
 
-// fragments: forward B operand of layer l, then (layers 1..4) the backward
-// (input-gradient) B operand, each [ksteps][ntiles][64 lanes] x 4 bf16
-__host__ __device__ constexpr int ffrag_count(int l) { return ksteps(kCin[l]) * ntiles(kCout[l]) * 64; }
+// fragments of the input-gradient kernel (layers 1..4; 16x16x16 form):
+// [ksteps][ntiles][64 lanes] x 4 bf16 each
 __host__ __device__ constexpr int bfrag_count(int l) { return ksteps(pad4(kCout[l])) * ntiles(kCin[l]) * 64; }
-__host__ __device__ constexpr int ffrag_total()
+// start of layer l's input-gradient fragments (l >= 1); bfrag_off(kCnnLayers) is their end
+__host__ __device__ constexpr int bfrag_off(int l)
 {
     int o = 0;
-    for (int i = 0; i < kCnnLayers; i++)
-        o += ffrag_count(i);
-    return o;
-}
-// start of layer l's forward (bwd = false) or backward (bwd = true, l >= 1)
-// fragments; frag_off(kCnnLayers, true) is the end of both
-__host__ __device__ constexpr int frag_off(int l, bool bwd)
-{
-    int o = 0;
-    for (int i = 0; i < kCnnLayers; i++) {
-        if (i == l && !bwd)
-            return o;
-        o += ffrag_count(i);
-    }
-    for (int i = 1; i < kCnnLayers; i++) {
-        if (i == l && bwd)
-            return o;
+    for (int i = 1; i < l; i++)
         o += bfrag_count(i);
-    }
     return o;
 }
 
@@ -73,7 +56,7 @@ __host__ __device__ constexpr int ksteps32(int cin) { return (9 * cin + 31) / 32
 __host__ __device__ constexpr int f2_count(int l) { return ksteps32(kCin[l]) * ntiles(kCout[l]) * 64; }
 __host__ __device__ constexpr int f2_off(int l)   // in u64
 {
-    int o = (frag_off(kCnnLayers, true) + 1) & ~1;
+    int o = (bfrag_off(kCnnLayers) + 1) & ~1;
     for (int i = 0; i < l; i++)
         o += 2 * f2_count(i);
     return o;
@@ -113,21 +96,21 @@ __device__ __forceinline__ uint16_t f64_to_bf16(double x)
 // fragment packing (from the fp32 parameter vector)
 // ---------------------------------------------------------------------------
 
+// B operand of the input gradient of layer l (1..4): B[k][n] = W[c][8 - tap][n]
+// for k = tap * pad4(cout) + c (spatially flipped, transposed weights)
 __global__ void k_pack(const float *__restrict__ theta, uint64_t *__restrict__ frag)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int)frag_off(kCnnLayers, true))
+    if (idx >= bfrag_off(kCnnLayers))
         return;
-    const bool bwd = idx >= ffrag_total();
-    int l = bwd ? 1 : 0;
-    while (l + 1 < kCnnLayers && idx >= frag_off(l + 1, bwd))
+    int l = 1;
+    while (l + 1 < kCnnLayers && idx >= bfrag_off(l + 1))
         l++;
-    const int local = idx - frag_off(l, bwd);
+    const int local = idx - bfrag_off(l);
     const int cin = kCin[l], cout = kCout[l];
     const float *W = theta + param_off(l);
-    // GEMM operand B[k][n] of this direction
-    const int kin = bwd ? pad4(cout) : cin;      // channels of the operand's input
-    const int nout = bwd ? cin : cout;
+    const int kin = pad4(cout);                  // channels of the operand's input (the output gradient)
+    const int nout = cin;
     const int nt_count = ntiles(nout);
     const int lane = local & 63;
     const int nt = (local >> 6) % nt_count;
@@ -139,9 +122,7 @@ __global__ void k_pack(const float *__restrict__ theta, uint64_t *__restrict__ f
         float v = 0.f;
         if (k < 9 * kin && n < nout) {
             const int tap = k / kin, c = k % kin;
-            if (!bwd)
-                v = W[(n * 9 + tap) * cin + c];                       // W[n][tap][c]
-            else if (c < cout)
+            if (c < cout)
                 v = W[(c * 9 + (8 - tap)) * cin + n];                 // W[c][flipped tap][n]
         }
         packed |= (uint64_t)f32_to_bf16(v) << (16 * e);
@@ -183,7 +164,7 @@ __global__ void k_pack2(const float *__restrict__ theta, uint64_t *__restrict__ 
 
 hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s)
 {
-    const int n = (int)frag_off(kCnnLayers, true);
+    const int n = bfrag_off(kCnnLayers);
     hipLaunchKernelGGL(k_pack, dim3((n + 255) / 256), dim3(256), 0, s, theta, frag);
     int n2 = 0;
     for (int l = 0; l < kCnnLayers; l++)
@@ -193,22 +174,21 @@ hipError_t cnn_pack(const float *theta, uint64_t *frag, hipStream_t s)
 }
 
 // ---------------------------------------------------------------------------
-// 3x3 convolution, implicit GEMM on MFMA
+// 3x3 convolution of the backward pass (input gradient), implicit GEMM on
+// v_mfma_f32_16x16x16_bf16: four K values per lane, one tap of four channels
 // ---------------------------------------------------------------------------
 
 constexpr int CV_TY = 8, CV_TX = 32;   // output tile of a block (4 waves x 4 M-tiles of 16 px)
 
-enum { EPI_RELU = 0, EPI_F32 = 1, EPI_MASK = 2, EPI_HEAD = 3 };
+enum { EPI_RELU = 0, EPI_F32 = 1, EPI_HEAD = 2 };   // forward epilogues (k_conv2)
 
-// out[p][n] = sum_{tap, c} B[tap*CIN + c][n] * x[p + tap][c]  (zero padding)
-//  EPI_RELU: + bias, ReLU, bfloat16 out [p][COUT]
-//  EPI_F32 : + bias, float out [p][COUT]
-//  EPI_MASK: * (mask[p][n] > 0), bfloat16 out [p][COUT] (input gradient through a ReLU)
-template <int CIN, int COUT, int EPI>
-__global__ __launch_bounds__(256) void k_conv(int H, int W, const uint16_t *__restrict__ x,
-                                              const uint64_t *__restrict__ frag, const float *__restrict__ bias,
-                                              const uint16_t *__restrict__ mask, uint16_t *__restrict__ y,
-                                              float *__restrict__ yf)
+// input gradient of a layer through the ReLU below it:
+// out[p][n] = (mask[p][n] > 0) * sum_{tap, c} B[tap*CIN + c][n] * x[p + tap][c]
+// (zero padding), bfloat16 out [p][COUT]
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void k_conv_grad(int H, int W, const uint16_t *__restrict__ x,
+                                                   const uint64_t *__restrict__ frag,
+                                                   const uint16_t *__restrict__ mask, uint16_t *__restrict__ y)
 {
     constexpr int KS = ksteps(CIN), NT = ntiles(COUT);
     constexpr int SY = CV_TY + 2, SX = CV_TX + 2;
@@ -271,7 +251,6 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const uint16_t *__re
             const int n = t * 16 + col;
             if (n >= COUT)
                 continue;
-            const float bv = (EPI != EPI_MASK) ? bias[n] : 0.f;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
                 const int gx = x0 + (m & 1) * 16 + grp * 4 + e;
@@ -279,25 +258,19 @@ __global__ __launch_bounds__(256) void k_conv(int H, int W, const uint16_t *__re
                     continue;
                 const size_t p = ibase + (size_t)gy * W + gx;
                 const float v = acc[m][t][e];
-                if (EPI == EPI_RELU) {
-                    y[p * COUT + n] = f32_to_bf16(fmaxf(v + bv, 0.f));
-                } else if (EPI == EPI_F32) {
-                    yf[p * COUT + n] = v + bv;
-                } else {
-                    const bool pass = (mask[p * COUT + n] & 0x7FFFu) != 0;
-                    y[p * COUT + n] = f32_to_bf16(pass ? v : 0.f);
-                }
+                const bool pass = (mask[p * COUT + n] & 0x7FFFu) != 0;
+                y[p * COUT + n] = f32_to_bf16(pass ? v : 0.f);
             }
         }
     }
 }
 
-template <int CIN, int COUT, int EPI>
-static hipError_t conv(int nimg, int H, int W, const uint16_t *x, const uint64_t *frag, const float *bias,
-                       const uint16_t *mask, uint16_t *y, float *yf, hipStream_t s)
+template <int CIN, int COUT>
+static hipError_t conv_grad(int nimg, int H, int W, const uint16_t *x, const uint64_t *frag, const uint16_t *mask,
+                            uint16_t *y, hipStream_t s)
 {
     dim3 grd((W + CV_TX - 1) / CV_TX, (H + CV_TY - 1) / CV_TY, nimg);
-    hipLaunchKernelGGL((k_conv<CIN, COUT, EPI>), grd, dim3(256), 0, s, H, W, x, frag, bias, mask, y, yf);
+    hipLaunchKernelGGL((k_conv_grad<CIN, COUT>), grd, dim3(256), 0, s, H, W, x, frag, mask, y);
     return hipGetLastError();
 }
 
@@ -779,16 +752,16 @@ hipError_t cnn_backward(const float *theta, const uint64_t *frag, const uint16_t
     hipError_t e;
     // layer 5 (16 -> 2): its output gradient is stored with 4 channels
     CNN_TRY((wgrad<16, 2, 4>(nimg, H, W, a4, dz5, part, grad + param_off(4), s)));
-    CNN_TRY((conv<4, 16, EPI_MASK>(nimg, H, W, dz5, frag + frag_off(4, true), nullptr, a4, g0, nullptr, s)));
+    CNN_TRY((conv_grad<4, 16>(nimg, H, W, dz5, frag + bfrag_off(4), a4, g0, s)));
     // layer 4 (32 -> 16)
     CNN_TRY((wgrad<32, 16, 16>(nimg, H, W, a3, g0, part, grad + param_off(3), s)));
-    CNN_TRY((conv<16, 32, EPI_MASK>(nimg, H, W, g0, frag + frag_off(3, true), nullptr, a3, g1, nullptr, s)));
+    CNN_TRY((conv_grad<16, 32>(nimg, H, W, g0, frag + bfrag_off(3), a3, g1, s)));
     // layer 3 (32 -> 32)
     CNN_TRY((wgrad<32, 32, 32>(nimg, H, W, a2, g1, part, grad + param_off(2), s)));
-    CNN_TRY((conv<32, 32, EPI_MASK>(nimg, H, W, g1, frag + frag_off(2, true), nullptr, a2, g0, nullptr, s)));
+    CNN_TRY((conv_grad<32, 32>(nimg, H, W, g1, frag + bfrag_off(2), a2, g0, s)));
     // layer 2 (16 -> 32)
     CNN_TRY((wgrad<16, 32, 32>(nimg, H, W, a1, g0, part, grad + param_off(1), s)));
-    CNN_TRY((conv<32, 16, EPI_MASK>(nimg, H, W, g0, frag + frag_off(1, true), nullptr, a1, g1, nullptr, s)));
+    CNN_TRY((conv_grad<32, 16>(nimg, H, W, g0, frag + bfrag_off(1), a1, g1, s)));
     // layer 1 (4 -> 16)
     CNN_TRY((wgrad<4, 16, 16>(nimg, H, W, x, g1, part, grad + param_off(0), s)));
     return hipSuccess;
