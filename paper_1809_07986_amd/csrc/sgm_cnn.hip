@@ -344,8 +344,8 @@ struct NetGlue {
 // ---------------------------------------------------------------------------
 // 3x3 convolution, forward, on v_mfma_f32_16x16x32_bf16
 //
-// A block computes an 8 x 64 output tile: wave w takes rows 2w and 2w+1,
-// four M-tiles of 16 pixels per row, all N-tiles.  The input tile and its
+// A block computes an 8 x 32 output tile: wave w takes rows 2w and 2w+1,
+// two M-tiles of 16 pixels per row, all N-tiles.  The input tile and its
 // one-pixel halo sit in LDS with a padded pixel stride (CIN + 8 values for
 // CIN >= 16), so that the 16-byte A reads of sixteen neighbouring pixels
 // fall in distinct banks; the layer's B fragments are read once into
@@ -357,7 +357,11 @@ struct NetGlue {
 // (FEAT) and the last applies the head to its outputs (EPI_HEAD).
 // ---------------------------------------------------------------------------
 
-constexpr int C2_TY = 8, C2_TX = 64, C2_SY = C2_TY + 2, C2_SX = C2_TX + 2;
+// 8 x 32 tiles: many small blocks keep the layer's staging, matrix work and
+// stores of different blocks overlapping (8 x 64: 83 us per frame network,
+// 4 x 64: 74, 8 x 32: 73, 4 x 128: 86)
+constexpr int C2_TY = 8, C2_TX = 32, C2_SY = C2_TY + 2, C2_SX = C2_TX + 2;
+constexpr int C2_RPW = C2_TY / 4;   // output rows per wave
 
 __host__ __device__ constexpr int c2_ps(int cin) { return cin >= 16 ? cin + 8 : cin; }   // LDS pixel stride
 __host__ __device__ constexpr int c2_out_bytes(int cout, int epi)
@@ -380,7 +384,7 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
     static_assert(!FEAT || CIN == 4, "the network input has four channels");
     static_assert(CIN == 4 || CIN == 16 || CIN == 32, "input channels");
     constexpr int KS = ksteps32(CIN), NT = ntiles(COUT), PS = c2_ps(CIN);
-    constexpr int MW = 2 * (C2_TX / 16);   // M-tiles per wave
+    constexpr int MW = C2_RPW * (C2_TX / 16);   // M-tiles per wave
     __shared__ __align__(16) uint16_t smem[c2_lds(CIN, COUT, EPI) / 2];
     const int img = blockIdx.z;
     const int y0 = blockIdx.y * C2_TY, x0 = blockIdx.x * C2_TX;
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
     for (int kk = 0; kk < KS; kk++) {
 #pragma unroll
         for (int m = 0; m < MW; m++) {
-            const int row = 2 * wave + m / (C2_TX / 16);          // output row in the tile
+            const int row = C2_RPW * wave + m / (C2_TX / 16);     // output row in the tile
             const int cx = (m % (C2_TX / 16)) * 16 + col;         // output column in the tile
             uint4 av;
             if (CIN == 32) {
@@ -502,7 +506,7 @@ __global__ __launch_bounds__(256) void k_conv2(int H, int W, const uint16_t *__r
         const float bv = bias[n];
 #pragma unroll
         for (int m = 0; m < MW; m++) {
-            const int row = 2 * wave + m / (C2_TX / 16);
+            const int row = C2_RPW * wave + m / (C2_TX / 16);
             const int px0 = row * C2_TX + (m % (C2_TX / 16)) * 16 + 4 * kg;
 #pragma unroll
             for (int e = 0; e < 4; e++) {
