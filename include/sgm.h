@@ -203,7 +203,7 @@ int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
  *     instead of 72 (results are identical; exercises the segment fix-up);
  *   SGM_DEBUG_ALT_HORIZONTAL  reduced frames use the other horizontal
  *     aggregation kernel than the one chosen for max_disp (segmented scanlines
- *     for 64 < max_disp <= 128, one wave per scanline otherwise); results are
+ *     for max_disp > 64, one wave per scanline otherwise); results are
  *     identical, so both kernels can be checked at every size. */
 #define SGM_DEBUG_STAGES 1
 #define SGM_DEBUG_SHORT_SEGMENTS 2
