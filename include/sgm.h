@@ -73,7 +73,9 @@ typedef struct {
     int32_t window_mode;        /* SGM_WIN_KSIGMA or SGM_WIN_LEARNED */
     int32_t gate_rerun;         /* 1: pixels failing the innovation test are matched again over
                                    the full range in the same frame and restart from that
-                                   measurement (the frame is matched twice) */
+                                   measurement.  The second pass recomputes only what changes:
+                                   along each path, from a widened pixel until the losses
+                                   rejoin the first pass's (results equal a full second pass) */
     double r_curv;              /* 0: every pixel's measurement variance is r.  > 0 (SGM_WIN_KSIGMA
                                    contexts): the variance of a pixel's measurement is estimated
                                    from the cost values at the neighbouring disparities (Section 3,
@@ -164,6 +166,9 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
  *   SGM_STAGE_CENSUS_L / _R  uint64 per pixel
  *   SGM_STAGE_LO / _HI       int32 per pixel (window of the last frame)
  *   SGM_STAGE_OFFSETS        uint32, width*height+1 entries
+ * (after a gate re-run frame, OFFSETS and PATH0 + k are available only in
+ * contexts with SGM_DEBUG_STAGES on; the others keep the first pass's offsets
+ * and store the widened pixels' losses apart, and refuse them with SGM_EINVAL)
  *   SGM_STAGE_COST           uint8 per cell (Hamming cost; recorded only while
  *                            sgm_set_debug(ctx, 1) is on)
  *   SGM_STAGE_SUM            uint16 per cell (S = sum of L_r; recorded only
@@ -204,10 +209,14 @@ int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);
  *   SGM_DEBUG_ALT_HORIZONTAL  reduced frames use the other horizontal
  *     aggregation kernel than the one chosen for max_disp (segmented scanlines
  *     for max_disp > 64, one wave per scanline otherwise); results are
- *     identical, so both kernels can be checked at every size. */
+ *     identical, so both kernels can be checked at every size;
+ *   SGM_DEBUG_DENSE_RERUN  the gate re-run's second pass takes the route used
+ *     when the widened pixels' full-range blocks do not fit beside the first
+ *     pass's cells (every pixel matched again); results are identical. */
 #define SGM_DEBUG_STAGES 1
 #define SGM_DEBUG_SHORT_SEGMENTS 2
 #define SGM_DEBUG_ALT_HORIZONTAL 4
+#define SGM_DEBUG_DENSE_RERUN 8
 int sgm_set_debug(sgm_context *ctx, int32_t on);
 
 /* Per-stage GPU time, for benchmarks.  While profiling is on, every frame

@@ -15,7 +15,7 @@ SGM_OK, SGM_EINVAL, SGM_ENOMEM, SGM_EHIP, SGM_ESTATE = 0, -1, -2, -3, -4
 FLAG_PRED, FLAG_RESET, FLAG_FULLWIN, FLAG_GATEFAIL = 1, 2, 4, 8
 WIN_KSIGMA, WIN_LEARNED = 0, 1
 LEARNED_WMAX = 32
-DEBUG_STAGES, DEBUG_SHORT_SEGMENTS, DEBUG_ALT_HORIZONTAL = 1, 2, 4
+DEBUG_STAGES, DEBUG_SHORT_SEGMENTS, DEBUG_ALT_HORIZONTAL, DEBUG_DENSE_RERUN = 1, 2, 4, 8
 CNN_NPARAMS = 19394
 (STAGE_CENSUS_L, STAGE_CENSUS_R, STAGE_LO, STAGE_HI, STAGE_OFFSETS, STAGE_COST, STAGE_SUM, STAGE_DHAT,
  STAGE_PM, STAGE_FLAGS, STAGE_DSTAR, STAGE_DZ, STAGE_STATUS) = range(13)

@@ -31,6 +31,7 @@ struct sgm_context {
     DevBuffers b;
     bool started;
     bool debug;
+    bool sparse_layout;         // the last frame's second pass kept the first pass's offsets (gate re-run)
     int device;
     Profiler prof;
     hipStream_t side;           // census and horizontal aggregation run here, forked from the caller's stream
@@ -111,7 +112,7 @@ void free_buffers(DevBuffers &b)
     void *all[] = {b.cen_l,  b.cen_r, b.win,    b.off,   b.scan_part, b.cost,  b.lr,    b.sum,     b.d,
                    b.p,      b.sflags, b.mask,  b.dhat,  b.pm,        b.flags, b.dstar, b.dz,      b.zkey,
                    b.zidx,   b.tgt,   b.dprime, b.pprime, b.has,      b.rw,    b.dw,    b.pw,      b.status,
-                   b.widened,
+                   b.rerun,  b.moved, b.touched, b.woff,
                    b.hflag,  b.nu,    b.nu_w,   b.feat,  b.act_a,     b.act_b, b.cnn_out, b.hw,    b.rpix,  b.kappa,
                    b.theta,  b.frag};
     for (void *p : all)
@@ -296,6 +297,7 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
     const bool learned = p.window_mode == SGM_WIN_LEARNED;
     if (learned && !ctx->has_model)
         return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
+    ctx->sparse_layout = false;
     prof_begin_frame(ctx->prof, s);
     int rc0 = start_census(ctx, left, right, pitch, s);
     if (rc0)
@@ -327,16 +329,34 @@ int reduced_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *rig
         // second matching pass and restart from its measurement; with no such
         // pixel the pass would reproduce the first one, and its launches read
         // the device-side count and return at once
+        const Geometry &g = ctx->g;
+        DevBuffers &b = ctx->b;
         mk.begin(SGM_PROF_RERUN);
-        e = launch_gate_widen(ctx->g, ctx->b, s);
-        if (e == hipSuccess)
-            e = launch_scan(ctx->g, ctx->b, s, ctx->b.widened);
+        // debug contexts match every pixel again, so that the stage read-backs
+        // show the second pass's plain ragged layout; the others take the
+        // sparse pass, or the dense one when the full-range blocks do not fit
+        const bool sparse = !ctx->debug;
+        // the dense route is launched where it can be taken; its launches
+        // read a skip word and return at once when the sparse route ran
+        const bool dense = !sparse || g.rr_dense || !g.rr_room;
+        const uint32_t *dense_skip = b.rerun + (sparse ? RR_SKIP_DENSE : RR_NW);
+        e = launch_gate_widen(g, b, sparse, s);
+        if (e == hipSuccess && sparse)
+            e = launch_rerun_walk(g, b, s);
+        if (e == hipSuccess && sparse) {
+            const float *rpix = p.window_mode == SGM_WIN_LEARNED ? b.rpix : nullptr;
+            e = launch_wta_correct(g, b, correct_const(p), 1, false, rpix, s, b.rerun + RR_SKIP_SPARSE, true);
+        }
+        if (e == hipSuccess && dense)
+            e = launch_scan(g, b, s, dense_skip);
         if (e != hipSuccess)
             return hip_fail(e, "gate re-run launch");
-        rc = run_matcher(ctx, 1, s, false, ctx->b.widened);
+        if (dense)
+            rc = run_matcher(ctx, 1, s, false, dense_skip);
         mk.end(SGM_PROF_RERUN);
         if (rc)
             return rc;
+        ctx->sparse_layout = sparse && !g.rr_dense;
     }
     prof_end_frame(ctx->prof);
     return SGM_OK;
@@ -346,6 +366,7 @@ int full_frame_impl(sgm_context *ctx, const uint8_t *left, const uint8_t *right,
 {
     if (ctx->prm.window_mode == SGM_WIN_LEARNED && !ctx->has_model)
         return fail(SGM_ESTATE, "learned-window context has no model (sgm_set_window_model)");
+    ctx->sparse_layout = false;
     prof_begin_frame(ctx->prof, s);
     int rc = start_census(ctx, left, right, pitch, s);
     if (rc)
@@ -426,8 +447,15 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     g.D = prm->max_disp;
     g.N = g.W * g.H;
     g.lr_stride = (((size_t)g.N * g.D) + 255) & ~(size_t)255;
+    // gate re-run contexts: room behind the first pass's cells for a
+    // full-range block of every pixel, so that the sparse second pass always
+    // fits (as long as offsets stay below 2^32)
+    g.rr_room = prm->gate_rerun && 2 * (size_t)g.N * g.D + 256 < ((size_t)1 << 32);
+    if (g.rr_room)
+        g.lr_stride = ((2 * (size_t)g.N * g.D) + 255) & ~(size_t)255;
     g.hseg = 72;
     g.halt = false;
+    g.rr_dense = false;
     g.cw = prm->census_w;
     g.ch = prm->census_h;
     g.nbits = g.cw * g.ch - 1;
@@ -465,7 +493,10 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(dalloc(&b.flags, N));
     A(dalloc(&b.dstar, N));
     A(dalloc(&b.dz, N));
-    A(dalloc(&b.widened, 1));
+    A(dalloc(&b.rerun, RR_WORDS + 3 * (size_t)gate_parts(g)));
+    A(dalloc(&b.moved, N));
+    A(dalloc(&b.touched, N));
+    A(dalloc(&b.woff, N));
     A(dalloc(&b.zkey, N));
     A(dalloc(&b.zidx, N));
     A(dalloc(&b.tgt, N));
@@ -540,6 +571,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     }
     ctx->started = false;
     ctx->debug = false;
+    ctx->sparse_layout = false;
     ctx->has_model = false;
     *out = ctx;
     return SGM_OK;
@@ -611,11 +643,12 @@ int sgm_set_debug(sgm_context *ctx, int32_t on)
 {
     if (!ctx)
         return fail(SGM_EINVAL, "context is NULL");
-    if (on & ~(SGM_DEBUG_STAGES | SGM_DEBUG_SHORT_SEGMENTS | SGM_DEBUG_ALT_HORIZONTAL))
+    if (on & ~(SGM_DEBUG_STAGES | SGM_DEBUG_SHORT_SEGMENTS | SGM_DEBUG_ALT_HORIZONTAL | SGM_DEBUG_DENSE_RERUN))
         return fail(SGM_EINVAL, "unknown debug bits 0x%x", on);
     ctx->debug = (on & SGM_DEBUG_STAGES) != 0;
     ctx->g.hseg = (on & SGM_DEBUG_SHORT_SEGMENTS) ? 48 : 72;
     ctx->g.halt = (on & SGM_DEBUG_ALT_HORIZONTAL) != 0;
+    ctx->g.rr_dense = (on & SGM_DEBUG_DENSE_RERUN) != 0;
     return SGM_OK;
 }
 
@@ -654,6 +687,7 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
     if (!lo || !hi || !dstar || !dz)
         return fail(SGM_EINVAL, "window or output pointer is NULL");
     hipStream_t s = as_stream(stream);
+    ctx->sparse_layout = false;
     prof_begin_frame(ctx->prof, s);
     rc = start_census(ctx, left, right, pitch, s);
     if (rc)
@@ -794,6 +828,9 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
     const void *src = nullptr;
     size_t need = 0;
     size_t M = 0;
+    if (ctx->sparse_layout && (stage == SGM_STAGE_OFFSETS || (stage >= SGM_STAGE_PATH0 && stage < SGM_STAGE_PATH0 + 8)))
+        return fail(SGM_EINVAL, "stage %d: the last frame's gate re-run kept the first pass's offsets and stored the "
+                    "widened pixels' losses apart; sgm_set_debug(ctx, SGM_DEBUG_STAGES) keeps the plain layout", stage);
     if (stage == SGM_STAGE_COST || stage == SGM_STAGE_SUM ||
         (stage >= SGM_STAGE_PATH0 && stage < SGM_STAGE_PATH0 + 8)) {
         int64_t m = 0;

@@ -910,35 +910,6 @@ hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t
     return hipGetLastError();
 }
 
-// pixels that failed the innovation test of the first pass search the full
-// range in the second (FULLWIN | GATEFAIL)
-// widens the windows of the pixels that failed the innovation test and counts
-// them into *widened (zeroed first by its own launch: a fill kernel, so the
-// sequence can be captured in a graph)
-__global__ void k_gate_widen(int N, int D, const uint8_t *__restrict__ mask, uint8_t *__restrict__ flags,
-                             uint16_t *__restrict__ win, uint32_t *__restrict__ widened)
-{
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool fail = t < N && mask[t];
-    const uint64_t bal = __ballot(fail);
-    if (bal && (threadIdx.x & 63) == __builtin_ctzll(bal))
-        atomicAdd(widened, (uint32_t)__popcll(bal));
-    if (!fail)
-        return;
-    flags[t] |= SGM_FLAG_FULLWIN | SGM_FLAG_GATEFAIL;
-    win[t] = (uint16_t)((D - 1) << 8);
-}
-
-__global__ void k_zero_count(uint32_t *p) { *p = 0u; }
-
-hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(1), 0, s, b.widened);
-    hipLaunchKernelGGL(k_gate_widen, dim3((g.N + 255) / 256), dim3(256), 0, s, g.N, g.D, b.mask, b.flags, b.win,
-                       b.widened);
-    return hipGetLastError();
-}
-
 // training targets of a predicted frame: e = dz_full - dhat, m = dz_full - gt
 // (clipped to +-16), weights we = [prediction], wm = we * [gt >= 0]
 __global__ void k_targets(int N, const uint8_t *__restrict__ flags, const double *__restrict__ dhat,

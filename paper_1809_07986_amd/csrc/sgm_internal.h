@@ -41,7 +41,10 @@ struct DevBuffers {
     uint8_t *has, *rw;
     double *dw, *pw;
     uint32_t *status;
-    uint32_t *widened;         // pixels widened by the innovation test in this frame (gate re-run)
+    uint32_t *rerun;           // gate re-run counters and switches of this frame [RR_WORDS]
+    uint8_t *moved;            // gate re-run: widened pixel whose window was not the full range
+    uint8_t *touched;          // gate re-run: pixel whose second-pass result may differ from the first
+    uint32_t *woff;            // gate re-run: offset of a moved pixel's full-range block
     uint8_t *hflag;            // horizontal aggregation: flagged segments [2][H][kHMaxSeg]
     // learned window (allocated in learned mode only, except nu / nu_w)
     double *nu;                // innovation of the last frame (0 without prediction)
@@ -55,11 +58,25 @@ struct DevBuffers {
     uint64_t *frag;            // bfloat16 MFMA operands of the parameters
 };
 
+// gate re-run counter block (DevBuffers::rerun), zeroed before each second pass
+enum {
+    RR_NW = 0,        // pixels widened by the innovation test
+    RR_NMOVED,        // ... of them, pixels whose window was narrower than the full range
+    RR_EXTRA,         // cells the widening adds (sum of D - width over the widened pixels)
+    RR_M1,            // cells of the first pass
+    RR_RANK,          // full-range blocks handed out so far
+    RR_SKIP_DENSE,    // skip word of the dense second pass: 0 unless the blocks did not fit
+    RR_SKIP_SPARSE,   // skip word of the sparse second pass: 0 when it does not run
+    RR_WORDS = 8
+};
+
 struct Geometry {
     int W, H, D, N;
     size_t lr_stride;          // bytes between the path-loss buffers: N*D rounded up to 256
     int hseg;                  // horizontal aggregation: pixels per scanline segment (72, or 48 in debug)
     bool halt;                 // reduced frames: the other horizontal kernel than the size-based choice
+    bool rr_dense;             // gate re-run: always take the dense second pass's fallback route (debug)
+    bool rr_room;              // gate re-run: the path buffers hold N*D cells more, so the sparse pass always fits
     int cw, ch, nbits;
     int p1, p2;
     int npaths;
@@ -96,9 +113,12 @@ int count_horizontal_paths(const Geometry &g);
 hipError_t launch_agg_h(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip = nullptr);
 hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_t s, const uint32_t *skip = nullptr);
 // mode 0: full frame (restart filter), 1: reduced frame (Kalman), 2: matcher only;
-// rpix: per-pixel measurement variance (NULL: cc.r)
+// rpix: per-pixel measurement variance (NULL: cc.r); sparse: only the pixels the
+// gate re-run's sparse second pass marked, the moved ones read from their
+// full-range blocks
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip = nullptr);
+                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip = nullptr,
+                              bool sparse = false);
 // prediction without the offset scan (launch_predict = this + launch_scan)
 hipError_t launch_predict_core(const Geometry &g, DevBuffers &b, const WarpConst &wc, const double *Tdev,
                                const CorrectConst &cc, hipStream_t s);
@@ -122,7 +142,14 @@ hipError_t launch_features(const Geometry &g, const DevBuffers &b, const uint8_t
 // a frame's window network: input, five layers and head (five launches)
 hipError_t cnn_forward_frame(const Geometry &g, DevBuffers &b, const uint8_t *left, int pitch, float k_sigma,
                              hipStream_t s);
-hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, hipStream_t s);
+// gate re-run: widen the windows of the pixels that failed the innovation test
+// (counts into b.rerun).  sparse: also mark them for the sparse second pass,
+// place the full-range blocks and set the two skip words
+hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, bool sparse, hipStream_t s);
+// blocks of the widening kernels (3 counters each follow the RR_WORDS of DevBuffers::rerun)
+int gate_parts(const Geometry &g);
+// the sparse second pass's scanline walks (all enabled paths, one launch)
+hipError_t launch_rerun_walk(const Geometry &g, DevBuffers &b, hipStream_t s);
 hipError_t launch_targets(const Geometry &g, const DevBuffers &b, const double *dz_full, const float *gt, float *tgt,
                           hipStream_t s);
 hipError_t launch_windows_to_lohi(const Geometry &g, const DevBuffers &b, int32_t *out, int which,

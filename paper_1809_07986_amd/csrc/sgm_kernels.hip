@@ -1853,6 +1853,419 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
 }
 
 // ---------------------------------------------------------------------------
+// gate re-run (Section 4's innovation test): pixels that failed it in the
+// first pass search the full range in a second matching pass and restart from
+// that measurement.
+//
+// Sparse second pass.  Along one path, Eq. 1 makes a pixel's L_r depend on the
+// previous pixel's only through that pixel's vector of L_r over its window
+// (and its minimum).  The second pass therefore differs from the first only
+// from a pixel whose window changed (a "moved" pixel: widened, and narrower
+// than the full range before) up to the first later pixel whose recomputed
+// vector equals the stored one; from there on the two passes agree again.
+// The first pass's L_r stay in the path buffers.  One wave per scanline of
+// every path walks it: it jumps from moved pixel to moved pixel, starts from
+// the previous pixel's stored L_r, recomputes Eq. 1 until the vector rejoins
+// the stored one, and writes what changed: in place for pixels that kept their
+// window, into a full-range block after the first pass's cells for the moved
+// pixels.  Pixels it wrote (and every widened pixel) are marked; the WTA and
+// the correction then run on the marked pixels only, and the others keep the
+// first pass's results, which a full second pass reproduces bit for bit.
+// When the blocks would not fit behind the first pass's cells, the dense
+// second pass (every pixel matched again) runs instead; the choice is made on
+// the device, and each route's launches read a skip word.
+// ---------------------------------------------------------------------------
+
+constexpr int GW_T = 1024;   // pixels per block of the widening and placement kernels
+
+// sum over a block of GW_T threads (every thread receives it); `red` holds
+// one word per wave
+__device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1)
+        v += (uint32_t)__shfl_xor((int)v, m);
+    __syncthreads();   // `red` may still be read from the previous call
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    uint32_t t = 0;
+#pragma unroll
+    for (int w = 0; w < GW_T / 64; w++)
+        t += red[w];
+    return t;
+}
+
+// widen the failed pixels' windows (FULLWIN | GATEFAIL); each block writes
+// its counts (widened, moved, added cells) to parts[3 * block]; with `moved`
+// set, also mark the pixels for the sparse pass
+__global__ __launch_bounds__(GW_T) void k_gate_widen(int N, int D, const uint8_t *__restrict__ mask,
+                                                     uint8_t *__restrict__ flags, uint16_t *__restrict__ win,
+                                                     const uint32_t *__restrict__ off, uint32_t *__restrict__ rr,
+                                                     uint32_t *__restrict__ parts, uint8_t *__restrict__ moved,
+                                                     uint8_t *__restrict__ touched)
+{
+    __shared__ uint32_t red[GW_T / 64];
+    const int t = blockIdx.x * GW_T + threadIdx.x;
+    const bool fail = t < N && mask[t];
+    const int w1 = fail ? (int)(win[t] >> 8) + 1 : D;
+    const bool mv = fail && w1 < D;
+    const uint32_t nw = block_sum(fail ? 1u : 0u, red);
+    const uint32_t nm = block_sum(mv ? 1u : 0u, red);
+    const uint32_t ex = block_sum((uint32_t)(D - w1), red);
+    if (threadIdx.x == 0) {
+        parts[3 * blockIdx.x] = nw;
+        parts[3 * blockIdx.x + 1] = nm;
+        parts[3 * blockIdx.x + 2] = ex;
+        if (blockIdx.x == 0)
+            rr[RR_M1] = off[N];
+    }
+    if (moved && t < N) {
+        moved[t] = mv ? 1 : 0;
+        touched[t] = fail ? 1 : 0;
+    }
+    if (!fail)
+        return;
+    flags[t] |= SGM_FLAG_FULLWIN | SGM_FLAG_GATEFAIL;
+    win[t] = (uint16_t)((D - 1) << 8);
+}
+
+// totals of the widening's block counts; with `sparse`, the full-range block
+// of every moved pixel at M1 + rank * D (rank: raster order among the moved
+// pixels) when they all fit in a path buffer (`cap` cells).  The skip words
+// pick the route, and the sparse route's cell count (first pass + widening)
+// goes to off[N].
+__global__ __launch_bounds__(GW_T) void k_gate_place(int N, int D, int nparts, size_t cap, int sparse, int force_dense,
+                                                     const uint32_t *__restrict__ parts,
+                                                     const uint8_t *__restrict__ moved, uint32_t *__restrict__ woff,
+                                                     uint32_t *__restrict__ rr, uint32_t *__restrict__ off)
+{
+    __shared__ uint32_t red[GW_T / 64];
+    uint32_t nw = 0, nm = 0, ex = 0, before = 0;
+    for (int i = threadIdx.x; i < nparts; i += GW_T) {
+        nw += parts[3 * i];
+        nm += parts[3 * i + 1];
+        ex += parts[3 * i + 2];
+        before += i < (int)blockIdx.x ? parts[3 * i + 1] : 0u;
+    }
+    nw = block_sum(nw, red);
+    nm = block_sum(nm, red);
+    ex = block_sum(ex, red);
+    before = block_sum(before, red);
+    const uint32_t m1 = rr[RR_M1];
+    const bool fits = sparse && !force_dense && (size_t)m1 + (size_t)nm * (size_t)D <= cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        rr[RR_NW] = nw;
+        rr[RR_NMOVED] = nm;
+        rr[RR_EXTRA] = ex;
+        rr[RR_SKIP_DENSE] = fits ? 0u : nw;
+        rr[RR_SKIP_SPARSE] = fits ? nw : 0u;
+        if (fits)
+            off[N] = m1 + ex;
+    }
+    if (!fits)
+        return;
+    // rank within the block: moved pixels of the lower waves, then of the lower lanes
+    const int t = blockIdx.x * GW_T + threadIdx.x;
+    const bool mv = t < N && moved[t];
+    const uint64_t b = __ballot(mv);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0)
+        red[wv] = (uint32_t)__popcll(b);
+    __syncthreads();
+    uint32_t rank = before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wv; w++)
+        rank += red[w];
+    if (mv)
+        woff[t] = m1 + rank * (uint32_t)D;
+}
+
+int gate_parts(const Geometry &g) { return (g.N + GW_T - 1) / GW_T; }
+
+hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, bool sparse, hipStream_t s)
+{
+    const int np = gate_parts(g);
+    uint32_t *parts = b.rerun + RR_WORDS;
+    hipLaunchKernelGGL(k_gate_widen, dim3(np), dim3(GW_T), 0, s, g.N, g.D, b.mask, b.flags, b.win, b.off, b.rerun,
+                       parts, sparse ? b.moved : (uint8_t *)nullptr, sparse ? b.touched : (uint8_t *)nullptr);
+    hipLaunchKernelGGL(k_gate_place, dim3(np), dim3(GW_T), 0, s, g.N, g.D, np, g.lr_stride, sparse ? 1 : 0,
+                       g.rr_dense ? 1 : 0, (const uint32_t *)parts, b.moved, b.woff, b.rerun, b.off);
+    return hipGetLastError();
+}
+
+struct WalkArgs {
+    const uint64_t *cl, *cr;
+    const uint16_t *win;
+    const uint32_t *off, *woff;
+    const uint8_t *moved;
+    uint8_t *touched;
+    uint8_t *lr;
+    size_t lr_stride;
+    int W, H, nbits, p1, p2, npaths;
+    int8_t rx[kMaxPaths], ry[kMaxPaths], slot[kMaxPaths];
+    int cbase[kMaxPaths + 1];   // first scanline of each listed path; cbase[npaths] = all scanlines
+    const uint32_t *skip;
+};
+
+constexpr int RW_T = 256;   // four waves per block, one scanline each
+
+// Eq. 1 at one pixel for a whole wave (lanes by disparity, chunk j holds
+// d = 64 j + lane): Ln = LBIG outside the window [lo, hi]
+template <int MAXCH>
+__device__ __forceinline__ void eq1_wave(const Chain<MAXCH> &st, int lane, bool first, uint64_t clp, int x, int lo,
+                                         int hi, const uint64_t (&crv)[MAXCH], int jlo, int jhi, int p1, int p2,
+                                         int nbits, int (&Ln)[MAXCH])
+{
+    const int mq = st.mq;
+    const int cap = first ? LBIG : mq + p2;
+    const int base = first ? 0 : -mq;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++) {
+        Ln[j] = LBIG;
+        if (j < jlo || j > jhi)
+            continue;
+        const int d = j * 64 + lane;
+        int pm = from_prev_lane<64>(st.Lp[j]);
+        int pp = from_next_lane<64>(st.Lp[j]);
+        if (j > 0) {
+            const int edge = __builtin_amdgcn_readlane(st.Lp[j - 1], 63);
+            pm = lane == 0 ? edge : pm;
+        }
+        if (j < MAXCH - 1) {
+            const int edge = __builtin_amdgcn_readlane(st.Lp[j + 1], 0);
+            pp = lane == 63 ? edge : pp;
+        }
+        const int best = first ? 0 : min(min(st.Lp[j], cap), min(pm, pp) + p1);
+        const int c = d > x ? nbits : __popcll(clp ^ crv[j]);
+        const bool in = (unsigned)(d - lo) <= (unsigned)(hi - lo);
+        Ln[j] = in ? c + best + base : LBIG;
+    }
+}
+
+// loads of one step of the walk: the right census at x - d and, for a pixel
+// that kept its window, its stored L_r, for every disparity of [lo, hi]
+template <int MAXCH>
+__device__ __forceinline__ void walk_loads(const uint64_t *crow, const uint8_t *lrk, int x, int lo, int hi,
+                                           uint32_t o, bool mvp, int lane, uint64_t (&crv)[MAXCH], int (&old)[MAXCH])
+{
+    const int jlo = lo >> 6, jhi = hi >> 6;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++) {
+        crv[j] = 0;
+        old[j] = LBIG;
+        if (j < jlo || j > jhi)
+            continue;
+        const int d = j * 64 + lane;
+        const bool in = (unsigned)(d - lo) <= (unsigned)(hi - lo);
+        if (in && d <= x)
+            crv[j] = crow[x - d];
+        if (in && !mvp)
+            old[j] = lrk[o + (uint32_t)(d - lo)];
+    }
+}
+
+template <int MAXCH, int P>
+__global__ __launch_bounds__(RW_T) void k_rerun_walk(WalkArgs a)
+{
+    if (pass_skipped(a.skip))
+        return;
+    const int c = blockIdx.x * (RW_T / 64) + (int)(threadIdx.x >> 6);
+    if (c >= a.cbase[a.npaths])
+        return;   // the whole wave
+    int pi = 0;
+    while (pi + 1 < a.npaths && c >= a.cbase[pi + 1])
+        pi++;
+    const int rx = a.rx[pi], ry = a.ry[pi], cc = c - a.cbase[pi];
+    const int W = a.W, H = a.H;
+    // the scanline's first pixel lies on the border the path enters from
+    const int x0 = rx > 0 ? 0 : W - 1, y0 = ry > 0 ? 0 : H - 1;
+    int sx, sy, len;
+    if (ry == 0) {
+        sx = x0, sy = cc, len = W;
+    } else if (rx == 0) {
+        sx = cc, sy = y0, len = H;
+    } else if (cc < W) {
+        sx = cc, sy = y0, len = min(H, rx > 0 ? W - cc : cc + 1);
+    } else {
+        sx = x0, sy = y0 + ry * (cc - W + 1);
+        len = min(W, ry > 0 ? H - sy : sy + 1);
+    }
+    const int p0 = sy * W + sx, dp = ry * W + rx;
+    const int lane = threadIdx.x & 63;
+    uint8_t *lrk = a.lr + (size_t)a.slot[pi] * a.lr_stride;
+    const int p1 = a.p1, p2 = a.p2, nbits = a.nbits;
+    Chain<MAXCH> st;
+#pragma unroll
+    for (int j = 0; j < MAXCH; j++)
+        st.Lp[j] = LBIG;
+    st.mq = 0;
+    bool dirty = false;   // the previous pixel's L_r differ from the first pass's
+    for (int t0 = 0; t0 < len; t0 += 64) {
+        // this batch's pixels, one per lane
+        const int tl = min(t0 + lane, len - 1);
+        const int pl = p0 + tl * dp;
+        const bool mvl = t0 + lane < len && a.moved[pl];
+        const uint64_t mvb = __ballot(mvl);
+        if (!dirty && !mvb)
+            continue;
+        const uint32_t bwin = a.win[pl];
+        const uint32_t boff = mvl ? a.woff[pl] : a.off[pl];
+        const uint64_t bcl = a.cl[pl];
+        const int n = min(64, len - t0);
+        int s = 0;
+        while (s < n) {
+            const bool cont = dirty;   // the group continues a dirty stretch
+            bool start = false;
+            uint32_t qwin = 0, qoff = 0;
+            if (!dirty) {
+                // next moved pixel of the batch; its predecessor kept the
+                // first pass's L_r (a moved predecessor would have left the
+                // scanline dirty)
+                const uint64_t rem = (mvb >> s) << s;
+                if (!rem)
+                    break;
+                s = __builtin_ctzll(rem);
+                start = t0 + s > 0;
+                if (s > 0) {
+                    qwin = (uint32_t)__builtin_amdgcn_readlane((int)bwin, s - 1);
+                    qoff = (uint32_t)__builtin_amdgcn_readlane((int)boff, s - 1);
+                } else if (start) {
+                    const int q = p0 + (t0 - 1) * dp;
+                    qwin = a.win[q];
+                    qoff = a.off[q];
+                }
+            }
+            // a group of steps whose loads are issued together (one memory
+            // latency per group): P steps where the scanline is already dirty
+            // (a stretch that has not rejoined tends to go on); from a moved
+            // pixel, the moved pixels that follow it (the scanline stays dirty
+            // through them) and two more
+            // (~(mvb >> s) is 0 only when s = 0 and all 64 pixels moved)
+            const uint64_t rest = ~(mvb >> s);
+            const int run = rest ? __builtin_ctzll(rest) : 64;
+            const int gn = min(n - s, cont ? P : min(run + 2, P));   // >= 1: every group advances s
+            uint64_t crv[P][MAXCH];
+            int old[P][MAXCH];
+#pragma unroll
+            for (int i = 0; i < P; i++) {
+                if (i >= gn)
+                    break;
+                const int si = s + i, t = t0 + si;
+                const uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)bwin, si);
+                const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)boff, si);
+                const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
+                walk_loads<MAXCH>(a.cr + (size_t)(sy + t * ry) * W, lrk, sx + t * rx, lo, hi, o,
+                                  (mvb >> si) & 1ull, lane, crv[i], old[i]);
+            }
+            if (start) {
+                const int qlo = (int)(qwin & 255), qhi = qlo + (int)(qwin >> 8);
+                int m = LBIG;
+#pragma unroll
+                for (int j = 0; j < MAXCH; j++) {
+                    const int d = j * 64 + lane;
+                    const bool in = (unsigned)(d - qlo) <= (unsigned)(qhi - qlo);
+                    st.Lp[j] = in ? (int)lrk[qoff + (uint32_t)(d - qlo)] : LBIG;
+                    m = min(m, st.Lp[j]);
+                }
+                st.mq = group_min_dpp<64>(m);
+            }
+            int done = gn;
+#pragma unroll
+            for (int i = 0; i < P; i++) {
+                if (i >= gn)
+                    break;
+                // Eq. 1 at the pixel of lane s + i
+                const int si = s + i, t = t0 + si;
+                const uint32_t wv = (uint32_t)__builtin_amdgcn_readlane((int)bwin, si);
+                const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)boff, si);
+                const uint64_t clp = readlane64(bcl, si);
+                const bool mvp = (mvb >> si) & 1ull;
+                const int lo = (int)(wv & 255), hi = lo + (int)(wv >> 8);
+                int Ln[MAXCH];
+                eq1_wave<MAXCH>(st, lane, t == 0, clp, sx + t * rx, lo, hi, crv[i], lo >> 6, hi >> 6, p1, p2, nbits,
+                                Ln);
+                bool neq = false;
+                int m = LBIG;
+#pragma unroll
+                for (int j = 0; j < MAXCH; j++) {
+                    neq |= Ln[j] != old[i][j];
+                    m = min(m, Ln[j]);
+                }
+                // a moved pixel always writes its block; another pixel writes
+                // (and is marked) only where its L_r changed
+                const bool changed = mvp || __ballot(neq) != 0ull;
+                if (changed) {
+#pragma unroll
+                    for (int j = 0; j < MAXCH; j++) {
+                        const int d = j * 64 + lane;
+                        if (Ln[j] != LBIG)
+                            lrk[o + (uint32_t)(d - lo)] = (uint8_t)Ln[j];
+                    }
+                    if (!mvp && lane == 0)
+                        a.touched[p0 + t * dp] = 1;
+                }
+                dirty = changed;
+#pragma unroll
+                for (int j = 0; j < MAXCH; j++)
+                    st.Lp[j] = Ln[j];
+                st.mq = group_min_dpp<64>(m);
+                if (!dirty) {
+                    done = i + 1;   // rejoined: the rest of the group is not needed
+                    break;
+                }
+            }
+            s += done;
+        }
+    }
+}
+
+hipError_t launch_rerun_walk(const Geometry &g, DevBuffers &b, hipStream_t s)
+{
+    WalkArgs a;
+    a.cl = b.cen_l;
+    a.cr = b.cen_r;
+    a.win = b.win;
+    a.off = b.off;
+    a.woff = b.woff;
+    a.moved = b.moved;
+    a.touched = b.touched;
+    a.lr = b.lr;
+    a.lr_stride = g.lr_stride;
+    a.W = g.W;
+    a.H = g.H;
+    a.nbits = g.nbits;
+    a.p1 = g.p1;
+    a.p2 = g.p2;
+    a.skip = b.rerun + RR_SKIP_SPARSE;
+    // horizontal scanlines (the longest) first in the grid
+    int n = 0, tot = 0;
+    for (int pass = 0; pass < 2; pass++)
+        for (int k = 0; k < g.npaths; k++) {
+            if ((g.ry[k] == 0) != (pass == 0))
+                continue;
+            a.rx[n] = g.rx[k];
+            a.ry[n] = g.ry[k];
+            a.slot[n] = (int8_t)k;
+            a.cbase[n] = tot;
+            tot += g.ry[k] == 0 ? g.H : g.rx[k] == 0 ? g.W : g.W + g.H - 1;
+            n++;
+        }
+    a.cbase[n] = tot;
+    a.npaths = n;
+    const dim3 grd((tot + RW_T / 64 - 1) / (RW_T / 64));
+    if (g.D <= 64)
+        hipLaunchKernelGGL((k_rerun_walk<1, 4>), grd, dim3(RW_T), 0, s, a);
+    else if (g.D <= 128)
+        hipLaunchKernelGGL((k_rerun_walk<2, 4>), grd, dim3(RW_T), 0, s, a);
+    else if (g.D <= 192)
+        hipLaunchKernelGGL((k_rerun_walk<3, 4>), grd, dim3(RW_T), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_rerun_walk<4, 4>), grd, dim3(RW_T), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // winner-takes-all (Section 2.3) with parabolic sub-pixel fit, then the
 // Kalman correction (Eq. 5-6) and the innovation test (Section 4).
 // A group of WG lanes handles one pixel: lanes sum the paths' L_r over the
@@ -1887,7 +2300,10 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
                                                        uint8_t *__restrict__ mask, uint8_t *__restrict__ sflags,
                                                        const float *__restrict__ rpix, double *__restrict__ nu_out,
                                                        const uint32_t *skip, float *__restrict__ rcurv_out,
-                                                       int32_t *__restrict__ kappa_out)
+                                                       int32_t *__restrict__ kappa_out,
+                                                       const uint8_t *__restrict__ touched,
+                                                       const uint8_t *__restrict__ moved,
+                                                       const uint32_t *__restrict__ woff)
 {
     if (pass_skipped(skip))
         return;
@@ -1897,8 +2313,12 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
     const int t = blockIdx.x * WNG + grp;
     if (t >= N)
         return;   // the whole group leaves together
+    // sparse gate re-run pass: an unmarked pixel keeps the first pass's
+    // results; a moved one reads its full-range block
+    if (touched && !touched[t])
+        return;
     uint16_t *ssum = ssum_lds + (size_t)grp * (D + 8);
-    const uint32_t o = off[t];
+    const uint32_t o = (moved && moved[t]) ? woff[t] : off[t];
     const uint32_t wv = win[t];
     // the correction's inputs are read with the window (every lane, no branch):
     // their latency overlaps the sums
@@ -1998,20 +2418,22 @@ __global__ __launch_bounds__(WTA_T) void k_wta_correct(int N, int D, int npaths,
 }
 
 hipError_t launch_wta_correct(const Geometry &g, DevBuffers &b, const CorrectConst &cc, int mode,
-                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip)
+                              bool debug_sum, const float *rpix, hipStream_t s, const uint32_t *skip, bool sparse)
 {
+    const uint8_t *touched = sparse ? b.touched : nullptr, *moved = sparse ? b.moved : nullptr;
+    const uint32_t *woff = sparse ? b.woff : nullptr;
     if (mode == 0)
         hipLaunchKernelGGL((k_wta_correct<16>), dim3((g.N + 15) / 16), dim3(WTA_T), (size_t)16 * (g.D + 8) * 2, s,
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu, skip, b.rpix, b.kappa);
+                       b.nu, skip, b.rpix, b.kappa, touched, moved, woff);
     else
         hipLaunchKernelGGL((k_wta_correct<8>), dim3((g.N + 31) / 32), dim3(WTA_T), (size_t)32 * (g.D + 8) * 2, s,
                            g.N, g.D, g.npaths, cc,
                        mode, b.lr, g.lr_stride, b.win, b.off, b.flags, b.dhat, b.pm,
                        debug_sum ? b.sum : (uint16_t *)nullptr, b.dstar, b.dz, b.d, b.p, b.mask, b.sflags, rpix,
-                       b.nu, skip, b.rpix, b.kappa);
+                       b.nu, skip, b.rpix, b.kappa, touched, moved, woff);
     return hipGetLastError();
 }
 

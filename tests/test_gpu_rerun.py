@@ -1,0 +1,85 @@
+"""Gate re-run (Section 4's innovation test, then a second matching pass):
+the sparse second pass against the dense one, through the C ABI.
+
+A context without debug stages recomputes, along each path, only from the
+widened pixels until the path losses rejoin the first pass's, and runs the
+WTA and the correction on the pixels it changed.  Its per-pixel results must
+equal, bit for bit, those of the two dense routes: the device-side fallback
+(SGM_DEBUG_DENSE_RERUN) and a debug-stages context, which matches every pixel
+again exactly as before.  The dense second pass itself is compared with the
+oracle in tests/test_gpu_learned.py (tiny and 1242x375x256 learned frames),
+which now run the sparse route as well.
+
+Tolerance: bit for bit on flags, windows, winners, sub-pixel measurements,
+innovations, filter state, masks and the cell count.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import stereo_synth as synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1809_07986_amd as sgmk  # noqa: E402
+from paper_1809_07986_amd import _native as NAT  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _np(t):
+    return t.cpu().numpy()
+
+
+def _outputs(g):
+    d, p, sf = (_np(t) for t in g.get_state())
+    out = {k: _np(g.stage(s)) for k, s in (("flags", NAT.STAGE_FLAGS), ("lo", NAT.STAGE_LO), ("hi", NAT.STAGE_HI),
+                                            ("dstar", NAT.STAGE_DSTAR), ("dz", NAT.STAGE_DZ), ("nu", NAT.STAGE_NU))}
+    out.update(d=d, p=p, sflags=sf, mask=_np(g.motion_mask()), cells=np.array([g.cost_cells()]))
+    return out
+
+
+# D = 64, 128, 160, 256: one to four 64-disparity chunks per lane in the walk
+@pytest.mark.parametrize("D", [64, 128, 160, 256])
+def test_sparse_rerun_equals_dense(D):
+    seq = synth.make_sequence("driving", frames=4, width=640, height=192, seed=7)
+    W, H = seq.cam.width, seq.cam.height
+    _say(f"gate re-run routes, {W}x{H}x{D}, frames 1-3")
+    routes = {"plain": NAT.DEBUG_STAGES, "sparse": 0, "fallback": NAT.DEBUG_DENSE_RERUN}
+    ctx = {}
+    for name, dbg in routes.items():
+        g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, gate_rerun=1)
+        g.set_debug(dbg)
+        g.full_frame(seq.left[0], seq.right[0])
+        ctx[name] = g
+    failed = 0
+    for k in (1, 2, 3):
+        outs = {}
+        for name, g in ctx.items():
+            g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
+            torch.cuda.synchronize()
+            outs[name] = _outputs(g)
+        ref = outs["plain"]
+        for name in ("sparse", "fallback"):
+            for key, v in ref.items():
+                assert np.array_equal(outs[name][key], v), (D, k, name, key)
+        failed += int(((ref["flags"] & NAT.FLAG_GATEFAIL) != 0).sum())
+    _say(f"  widened pixels over the three frames: {failed}")
+    assert failed > 0, "the moving cars should fail the innovation test"
+    # the sparse route kept the first pass's offsets: their read-back is refused
+    with pytest.raises(sgmk.SgmError):
+        ctx["sparse"].stage(NAT.STAGE_OFFSETS)
+    with pytest.raises(sgmk.SgmError):
+        ctx["sparse"].stage(NAT.STAGE_PATH0)
+    # the dense routes keep the plain layout
+    assert ctx["fallback"].stage(NAT.STAGE_OFFSETS).numel() == W * H + 1
+    for g in ctx.values():
+        g.close()
