@@ -47,21 +47,20 @@ def _outputs(g):
     return out
 
 
-# D = 64, 128, 160, 256: one to four 64-disparity chunks per lane in the walk
-@pytest.mark.parametrize("D", [64, 128, 160, 256])
-def test_sparse_rerun_equals_dense(D):
-    seq = synth.make_sequence("driving", frames=4, width=640, height=192, seed=7)
+def _compare_routes(seq, D, frames=(1, 2, 3), label="", **over):
+    """Run the three routes on the same frames and compare them; return the
+    number of widened pixels over those frames and the three contexts."""
     W, H = seq.cam.width, seq.cam.height
-    _say(f"gate re-run routes, {W}x{H}x{D}, frames 1-3")
+    _say(f"gate re-run routes, {W}x{H}x{D} {label}, frames {frames}")
     routes = {"plain": NAT.DEBUG_STAGES, "sparse": 0, "fallback": NAT.DEBUG_DENSE_RERUN}
     ctx = {}
     for name, dbg in routes.items():
-        g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, gate_rerun=1)
+        g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, gate_rerun=1, **over)
         g.set_debug(dbg)
         g.full_frame(seq.left[0], seq.right[0])
         ctx[name] = g
     failed = 0
-    for k in (1, 2, 3):
+    for k in frames:
         outs = {}
         for name, g in ctx.items():
             g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
@@ -70,9 +69,18 @@ def test_sparse_rerun_equals_dense(D):
         ref = outs["plain"]
         for name in ("sparse", "fallback"):
             for key, v in ref.items():
-                assert np.array_equal(outs[name][key], v), (D, k, name, key)
+                assert np.array_equal(outs[name][key], v), (D, label, k, name, key)
         failed += int(((ref["flags"] & NAT.FLAG_GATEFAIL) != 0).sum())
-    _say(f"  widened pixels over the three frames: {failed}")
+    _say(f"  widened pixels: {failed} of {len(frames) * W * H}")
+    return failed, ctx
+
+
+# D = 64, 128, 160, 256: one to four 64-disparity chunks per lane in the walk
+@pytest.mark.parametrize("D", [64, 128, 160, 256])
+def test_sparse_rerun_equals_dense(D):
+    seq = synth.make_sequence("driving", frames=4, width=640, height=192, seed=7)
+    W, H = seq.cam.width, seq.cam.height
+    failed, ctx = _compare_routes(seq, D)
     assert failed > 0, "the moving cars should fail the innovation test"
     # the sparse route kept the first pass's offsets: their read-back is refused
     with pytest.raises(sgmk.SgmError):
@@ -81,5 +89,38 @@ def test_sparse_rerun_equals_dense(D):
         ctx["sparse"].stage(NAT.STAGE_PATH0)
     # the dense routes keep the plain layout
     assert ctx["fallback"].stage(NAT.STAGE_OFFSETS).numel() == W * H + 1
+    for g in ctx.values():
+        g.close()
+
+
+def test_sparse_rerun_when_every_pixel_fails():
+    # a gate nothing passes: every predicted pixel is widened, whole 64-pixel
+    # batches of every scanline are moved, and the full-range blocks fill most
+    # of the room reserved behind the first pass's cells
+    seq = synth.make_sequence("driving", frames=3, width=640, height=192, seed=7)
+    failed, ctx = _compare_routes(seq, 128, frames=(1, 2), label="gate 1e-12", chi2_gate=1e-12)
+    n = seq.cam.width * seq.cam.height
+    assert failed > 1.6 * n, "nearly every pixel should fail the innovation test"
+    for g in ctx.values():
+        g.close()
+
+
+@pytest.mark.parametrize("mask", [0x0F, 0xF0, 0x41])
+def test_sparse_rerun_path_subsets(mask):
+    # subsets of the paths (Table 2's sets and a pair) with the paper's census
+    # and penalties (Table 1)
+    seq = synth.make_sequence("driving", frames=3, width=640, height=192, seed=7)
+    failed, ctx = _compare_routes(seq, 128, frames=(1, 2), label=f"paths 0x{mask:02x}", path_mask=mask,
+                                  census_w=5, census_h=5, p1=6, p2=65)
+    assert failed > 0
+    for g in ctx.values():
+        g.close()
+
+
+def test_sparse_rerun_small_image():
+    # scanlines shorter than one 64-pixel batch, and more disparities than columns
+    seq = synth.make_sequence("tiny", frames=3, width=37, height=19, seed=3)
+    failed, ctx = _compare_routes(seq, 64, frames=(1, 2), label="37x19", chi2_gate=0.5)
+    assert failed > 0
     for g in ctx.values():
         g.close()
