@@ -1876,7 +1876,7 @@ hipError_t launch_agg_v(const Geometry &g, DevBuffers &b, bool dense, hipStream_
 // the device, and each route's launches read a skip word.
 // ---------------------------------------------------------------------------
 
-constexpr int GW_T = 1024;   // pixels per block of the widening and placement kernels
+constexpr int GW_T = 1024, GW_PER = 4, GW_BLOCK = GW_T * GW_PER;   // widening and placement: pixels per thread, block
 
 // sum over a block of GW_T threads (every thread receives it); `red` holds
 // one word per wave
@@ -1896,9 +1896,9 @@ __device__ __forceinline__ uint32_t block_sum(uint32_t v, uint32_t *red)
     return t;
 }
 
-// widen the failed pixels' windows (FULLWIN | GATEFAIL); each block writes
-// its counts (widened, moved, added cells) to parts[3 * block]; with `moved`
-// set, also mark the pixels for the sparse pass
+// widen the failed pixels' windows (FULLWIN | GATEFAIL); each block of
+// GW_BLOCK pixels writes its counts (widened, moved, added cells) to
+// parts[3 * block]; with `moved` set, also mark the pixels for the sparse pass
 __global__ __launch_bounds__(GW_T) void k_gate_widen(int N, int D, const uint8_t *__restrict__ mask,
                                                      uint8_t *__restrict__ flags, uint16_t *__restrict__ win,
                                                      const uint32_t *__restrict__ off, uint32_t *__restrict__ rr,
@@ -1906,13 +1906,29 @@ __global__ __launch_bounds__(GW_T) void k_gate_widen(int N, int D, const uint8_t
                                                      uint8_t *__restrict__ touched)
 {
     __shared__ uint32_t red[GW_T / 64];
-    const int t = blockIdx.x * GW_T + threadIdx.x;
-    const bool fail = t < N && mask[t];
-    const int w1 = fail ? (int)(win[t] >> 8) + 1 : D;
-    const bool mv = fail && w1 < D;
-    const uint32_t nw = block_sum(fail ? 1u : 0u, red);
-    const uint32_t nm = block_sum(mv ? 1u : 0u, red);
-    const uint32_t ex = block_sum((uint32_t)(D - w1), red);
+    const int base = blockIdx.x * GW_BLOCK + threadIdx.x * GW_PER;
+    uint32_t nw = 0, nm = 0, ex = 0;
+#pragma unroll
+    for (int i = 0; i < GW_PER; i++) {
+        const int t = base + i;
+        const bool fail = t < N && mask[t];
+        const int w1 = fail ? (int)(win[t] >> 8) + 1 : D;
+        const bool mv = fail && w1 < D;
+        nw += fail ? 1u : 0u;
+        nm += mv ? 1u : 0u;
+        ex += (uint32_t)(D - w1);
+        if (moved && t < N) {
+            moved[t] = mv ? 1 : 0;
+            touched[t] = fail ? 1 : 0;
+        }
+        if (fail) {
+            flags[t] |= SGM_FLAG_FULLWIN | SGM_FLAG_GATEFAIL;
+            win[t] = (uint16_t)((D - 1) << 8);
+        }
+    }
+    nw = block_sum(nw, red);
+    nm = block_sum(nm, red);
+    ex = block_sum(ex, red);
     if (threadIdx.x == 0) {
         parts[3 * blockIdx.x] = nw;
         parts[3 * blockIdx.x + 1] = nm;
@@ -1920,27 +1936,20 @@ __global__ __launch_bounds__(GW_T) void k_gate_widen(int N, int D, const uint8_t
         if (blockIdx.x == 0)
             rr[RR_M1] = off[N];
     }
-    if (moved && t < N) {
-        moved[t] = mv ? 1 : 0;
-        touched[t] = fail ? 1 : 0;
-    }
-    if (!fail)
-        return;
-    flags[t] |= SGM_FLAG_FULLWIN | SGM_FLAG_GATEFAIL;
-    win[t] = (uint16_t)((D - 1) << 8);
 }
 
-// totals of the widening's block counts; with `sparse`, the full-range block
-// of every moved pixel at M1 + rank * D (rank: raster order among the moved
-// pixels) when they all fit in a path buffer (`cap` cells).  The skip words
-// pick the route, and the sparse route's cell count (first pass + widening)
-// goes to off[N].
+// totals of the widening's block counts (few: every block reads them all);
+// with `sparse`, the full-range block of every moved pixel at M1 + rank * D
+// (rank: raster order among the moved pixels) when they all fit in a path
+// buffer (`cap` cells).  The skip words pick the route, and the sparse route's
+// cell count (first pass + widening) goes to off[N].
 __global__ __launch_bounds__(GW_T) void k_gate_place(int N, int D, int nparts, size_t cap, int sparse, int force_dense,
                                                      const uint32_t *__restrict__ parts,
                                                      const uint8_t *__restrict__ moved, uint32_t *__restrict__ woff,
                                                      uint32_t *__restrict__ rr, uint32_t *__restrict__ off)
 {
     __shared__ uint32_t red[GW_T / 64];
+    __shared__ uint32_t tot;
     uint32_t nw = 0, nm = 0, ex = 0, before = 0;
     for (int i = threadIdx.x; i < nparts; i += GW_T) {
         nw += parts[3 * i];
@@ -1964,24 +1973,24 @@ __global__ __launch_bounds__(GW_T) void k_gate_place(int N, int D, int nparts, s
             off[N] = m1 + ex;
     }
     if (!fits)
-        return;
-    // rank within the block: moved pixels of the lower waves, then of the lower lanes
-    const int t = blockIdx.x * GW_T + threadIdx.x;
-    const bool mv = t < N && moved[t];
-    const uint64_t b = __ballot(mv);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0)
-        red[wv] = (uint32_t)__popcll(b);
-    __syncthreads();
-    uint32_t rank = before + (uint32_t)__popcll(b & ((1ull << lane) - 1ull));
-    for (int w = 0; w < wv; w++)
-        rank += red[w];
-    if (mv)
-        woff[t] = m1 + rank * (uint32_t)D;
+        return;   // uniform over the grid
+    // ranks: moved pixels of the blocks before, then of the threads before, then of this thread's
+    const int base = blockIdx.x * GW_BLOCK + threadIdx.x * GW_PER;
+    bool mv[GW_PER];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < GW_PER; i++) {
+        mv[i] = base + i < N && moved[base + i];
+        cnt += mv[i] ? 1u : 0u;
+    }
+    uint32_t rank = before + block_excl_scan(cnt, &tot);
+#pragma unroll
+    for (int i = 0; i < GW_PER; i++)
+        if (mv[i])
+            woff[base + i] = m1 + (rank++) * (uint32_t)D;
 }
 
-int gate_parts(const Geometry &g) { return (g.N + GW_T - 1) / GW_T; }
+int gate_parts(const Geometry &g) { return (g.N + GW_BLOCK - 1) / GW_BLOCK; }
 
 hipError_t launch_gate_widen(const Geometry &g, DevBuffers &b, bool sparse, hipStream_t s)
 {

@@ -47,7 +47,7 @@ def _outputs(g):
     return out
 
 
-def _compare_routes(seq, D, frames=(1, 2, 3), label="", **over):
+def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, **over):
     """Run the three routes on the same frames and compare them; return the
     number of widened pixels over those frames and the three contexts."""
     W, H = seq.cam.width, seq.cam.height
@@ -57,6 +57,8 @@ def _compare_routes(seq, D, frames=(1, 2, 3), label="", **over):
     for name, dbg in routes.items():
         g = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline, gate_rerun=1, **over)
         g.set_debug(dbg)
+        if model is not None:
+            g.set_window_model(model)
         g.full_frame(seq.left[0], seq.right[0])
         ctx[name] = g
     failed = 0
@@ -121,6 +123,18 @@ def test_sparse_rerun_small_image():
     # scanlines shorter than one 64-pixel batch, and more disparities than columns
     seq = synth.make_sequence("tiny", frames=3, width=37, height=19, seed=3)
     failed, ctx = _compare_routes(seq, 64, frames=(1, 2), label="37x19", chi2_gate=0.5)
+    assert failed > 0
+    for g in ctx.values():
+        g.close()
+
+
+def test_sparse_rerun_full_hd_learned():
+    # the combined workload's stream size: 1920x1080, D = 256, learned windows
+    # (shipped network) and near cars; many placement blocks, long scanlines
+    seq = synth.make_sequence("learned", frames=3, width=1920, height=1080, seed=11, cars=10, near=2.4,
+                              f=0.58 * 1920)
+    failed, ctx = _compare_routes(seq, 256, frames=(1, 2), label="learned", model=sgmk.load_window_model(),
+                                  window_mode=NAT.WIN_LEARNED)
     assert failed > 0
     for g in ctx.values():
         g.close()
