@@ -262,6 +262,45 @@ def test_single_direction_geometry():
         assert touched == expect, (k, sorted(touched))
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_second_pass_differs_only_until_losses_rejoin(seed):
+    # Gate re-run (Section 4's innovation test, then a second matching pass):
+    # the second pass widens some pixels to the full range.  Eq. 1 sees the
+    # previous pixel on a path only through its vector of L_r, so a pixel that
+    # kept its window and whose predecessor's L_r did not change has unchanged
+    # L_r: the two passes differ from a widened pixel up to the first pixel
+    # whose losses agree again, and nowhere else.
+    rng = np.random.default_rng(300 + seed)
+    H, W, D = 10, 14, 16
+    C = rng.integers(0, 63, (H, W, D)).astype(np.int32)
+    lo1, hi1 = synth.random_windows(rng, H, W, D, max_width=6, full_frac=0.1)
+    moved = rng.random((H, W)) < 0.08
+    lo2 = np.where(moved, 0, lo1).astype(np.int32)
+    hi2 = np.where(moved, D - 1, hi1).astype(np.int32)
+    _, L1 = O.aggregate(C, lo1, hi1, 7, 86, want_lr=True)
+    _, L2 = O.aggregate(C, lo2, hi2, 7, 86, want_lr=True)
+    d = np.arange(D)
+    in1 = (d >= lo1[..., None]) & (d <= hi1[..., None])
+    kept = rejoined = differ = 0
+    for k in range(8):
+        rx, ry = O.PATH_DX[k], O.PATH_DY[k]
+        same = np.all(np.where(in1, L1[k] == L2[k], True), axis=2)
+        for y in range(H):
+            for x in range(W):
+                if moved[y, x]:
+                    continue
+                qy, qx = y - ry, x - rx
+                first = not (0 <= qy < H and 0 <= qx < W)
+                if first or (not moved[qy, qx] and same[qy, qx]):
+                    assert same[y, x], (k, y, x)
+                    kept += 1
+                elif same[y, x]:
+                    rejoined += 1
+                else:
+                    differ += 1
+    assert kept > 0 and rejoined > 0 and differ > 0, (kept, rejoined, differ)
+
+
 # ---------------------------------------------------------------- WTA / subpixel
 
 def test_wta_argmin_lowest_on_ties():
