@@ -47,7 +47,7 @@ def _outputs(g):
     return out
 
 
-def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, **over):
+def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, extra=(), **over):
     """Run the three routes on the same frames and compare them; return the
     number of widened pixels over those frames and the three contexts."""
     W, H = seq.cam.width, seq.cam.height
@@ -68,6 +68,7 @@ def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, **over):
             g.reduced_frame(seq.left[k], seq.right[k], seq.T[k])
             torch.cuda.synchronize()
             outs[name] = _outputs(g)
+            outs[name].update({f"stage{st}": _np(g.stage(st)) for st in extra})
         ref = outs["plain"]
         for name in ("sparse", "fallback"):
             for key, v in ref.items():
@@ -137,4 +138,54 @@ def test_sparse_rerun_full_hd_learned():
                                   window_mode=NAT.WIN_LEARNED)
     assert failed > 0
     for g in ctx.values():
+        g.close()
+
+
+def test_sparse_rerun_with_curvature_variance():
+    # per-pixel measurement variance from the cost curvature (r_curv): the
+    # sparse pass's WTA writes kappa and r only for the pixels it changed
+    seq = synth.make_sequence("driving", frames=3, width=640, height=192, seed=7)
+    failed, ctx = _compare_routes(seq, 128, frames=(1, 2), label="r_curv", r_curv=8.31,
+                                  extra=(NAT.STAGE_KAPPA, NAT.STAGE_RPIX))
+    assert failed > 0
+    for g in ctx.values():
+        g.close()
+
+
+def test_sparse_rerun_in_a_batch():
+    # the batched step runs every stream's frame, second pass included, on
+    # concurrent lanes: each stream against a single context on the dense route
+    streams = [dict(width=320, height=96, max_disp=64, f=350.0, seed=11),
+               dict(width=256, height=128, max_disp=96, f=300.0, seed=13),
+               dict(width=200, height=72, max_disp=160, f=160.0, seed=12)]
+    seqs = [synth.make_sequence("tiny", frames=3, seed=st["seed"], width=st["width"], height=st["height"],
+                                max_disp=st["max_disp"], f=st["f"]) for st in streams]
+    prm = [dict(width=st["width"], height=st["height"], max_disp=st["max_disp"], f=st["f"], baseline=0.54,
+                gate_rerun=1, chi2_gate=0.5) for st in streams]
+    _say("gate re-run in a batch of 3 uneven streams vs single dense-route contexts")
+    b = sgmk.SgmBatch(prm)
+    singles = []
+    for i, (pr, q) in enumerate(zip(prm, seqs)):
+        b.load(i, q.left[0], q.right[0])
+        g = sgmk.ReducedSGM(**pr)
+        g.set_debug(NAT.DEBUG_STAGES)
+        g.full_frame(q.left[0], q.right[0])
+        singles.append(g)
+    b.full()
+    failed = 0
+    for k in (1, 2):
+        for i, q in enumerate(seqs):
+            b.load(i, q.left[k], q.right[k])
+        b.step(np.stack([q.T[k] for q in seqs]))
+        for g, q in zip(singles, seqs):
+            g.reduced_frame(q.left[k], q.right[k], q.T[k])
+        torch.cuda.synchronize()
+        for i, (c, g) in enumerate(zip(b.contexts, singles)):
+            got, ref = _outputs(c), _outputs(g)
+            for key, v in ref.items():
+                assert np.array_equal(got[key], v), (k, i, key)
+            failed += int(((ref["flags"] & NAT.FLAG_GATEFAIL) != 0).sum())
+    _say(f"  widened pixels: {failed}")
+    assert failed > 0
+    for g in singles:
         g.close()
