@@ -78,8 +78,9 @@ def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, extra=(), **
     return failed, ctx
 
 
-# D = 64, 128, 160, 256: one to four 64-disparity chunks per lane in the walk
-@pytest.mark.parametrize("D", [64, 128, 160, 256])
+# D = 37, 64, 128, 160, 256: one to four 64-disparity chunks per lane in the walk
+# (37: full-range blocks at offsets that are not multiples of four)
+@pytest.mark.parametrize("D", [37, 64, 128, 160, 256])
 def test_sparse_rerun_equals_dense(D):
     seq = synth.make_sequence("driving", frames=4, width=640, height=192, seed=7)
     W, H = seq.cam.width, seq.cam.height
