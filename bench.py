@@ -493,11 +493,15 @@ def bench_learned(args):
     for name, kw in variants.items():
         g = make(kw)
         cells, bad, nval = 0, 0, 0
+        widened, moved = 0, 0
         for k in range(1, seq.frames):
             g.reduced_frame(Ls[k], Rs[k], seq.T[k])
             cells += g.cost_cells()
             bad += int(((g.disparity() - gts[k]).abs() > 3)[vals[k]].sum())
             nval += int(vals[k].sum())
+            if kw.get("gate_rerun"):
+                cnt = g.stage(sgmk.N.STAGE_RERUN).cpu().tolist()
+                widened, moved = widened + cnt[0], moved + cnt[1]
         g.close()
         g = make(kw)
         for i in range(warm):
@@ -517,6 +521,11 @@ def bench_learned(args):
                      "cells_per_frame": round(cells / (seq.frames - 1), 1),
                      "bad_px_gt3": round(bad / max(nval, 1), 6),
                      "stage_ms": {k: round(v / max(nprof, 1), 5) for k, v in prof.items()}}
+        if kw.get("gate_rerun"):
+            # the re-run's fallback: pixels widened to the full range by the innovation
+            # test, and those of them whose window was narrower before (frames 1-19)
+            res[name]["widened_fraction"] = round(widened / ((seq.frames - 1) * W * H), 5)
+            res[name]["moved_fraction"] = round(moved / ((seq.frames - 1) * W * H), 5)
     gf = sgmk.ReducedSGM(W, H, D, f=seq.cam.f, baseline=seq.cam.baseline)
     for k in range(3):
         gf.full_frame(Ls[k], Rs[k])

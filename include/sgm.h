@@ -191,6 +191,10 @@ int sgm_match_windows(sgm_context *ctx, const uint8_t *left, const uint8_t *righ
  * curvature measurement variance (r_curv > 0 contexts, last frame):
  *   SGM_STAGE_KAPPA          int32 per pixel: kappa of the sub-pixel parabola, 0 where
  *                            d* lies on a window edge
+ * gate re-run (gate_rerun contexts, the last reduced frame; zeros before any):
+ *   SGM_STAGE_RERUN          uint32 [3]: pixels widened by the innovation test, those of
+ *                            them whose window was narrower than the full range, and
+ *                            the cells the widening added to the frame
  * sgm_cost_cells() synchronises the stream and returns the cell count M. */
 enum {
     SGM_STAGE_CENSUS_L = 0, SGM_STAGE_CENSUS_R, SGM_STAGE_LO, SGM_STAGE_HI, SGM_STAGE_OFFSETS,
@@ -198,7 +202,7 @@ enum {
     SGM_STAGE_DSTAR, SGM_STAGE_DZ, SGM_STAGE_STATUS,
     SGM_STAGE_PATH0 = 16,
     SGM_STAGE_NU = 32, SGM_STAGE_NU_W, SGM_STAGE_FEATURES, SGM_STAGE_CNN_OUT, SGM_STAGE_HALFWIDTH,
-    SGM_STAGE_RPIX, SGM_STAGE_KAPPA
+    SGM_STAGE_RPIX, SGM_STAGE_KAPPA, SGM_STAGE_RERUN
 };
 int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void *stream);
 int sgm_cost_cells(sgm_context *ctx, int64_t *cells, void *stream);

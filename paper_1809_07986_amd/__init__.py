@@ -199,7 +199,7 @@ class ReducedSGM:
                  N.STAGE_FLAGS: torch.uint8, N.STAGE_DSTAR: torch.int32, N.STAGE_DZ: torch.float64,
                  N.STAGE_STATUS: torch.int32, N.STAGE_NU: torch.float64, N.STAGE_NU_W: torch.float64,
                  N.STAGE_FEATURES: torch.int16, N.STAGE_CNN_OUT: torch.float32, N.STAGE_HALFWIDTH: torch.float32,
-                 N.STAGE_RPIX: torch.float32, N.STAGE_KAPPA: torch.int32}
+                 N.STAGE_RPIX: torch.float32, N.STAGE_KAPPA: torch.int32, N.STAGE_RERUN: torch.int32}
 
     def stage(self, stage: int) -> torch.Tensor:
         """Intermediate result of the last frame (see include/sgm.h)."""
@@ -210,6 +210,8 @@ class ReducedSGM:
             count = npx + 1
         elif stage == N.STAGE_STATUS:
             count = 1
+        elif stage == N.STAGE_RERUN:
+            count = 3
         elif stage == N.STAGE_FEATURES:
             count = npx * 4
         elif stage == N.STAGE_CNN_OUT:

@@ -20,7 +20,8 @@ CNN_NPARAMS = 19394
 (STAGE_CENSUS_L, STAGE_CENSUS_R, STAGE_LO, STAGE_HI, STAGE_OFFSETS, STAGE_COST, STAGE_SUM, STAGE_DHAT,
  STAGE_PM, STAGE_FLAGS, STAGE_DSTAR, STAGE_DZ, STAGE_STATUS) = range(13)
 STAGE_PATH0 = 16
-(STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX, STAGE_KAPPA) = range(32, 39)
+(STAGE_NU, STAGE_NU_W, STAGE_FEATURES, STAGE_CNN_OUT, STAGE_HALFWIDTH, STAGE_RPIX, STAGE_KAPPA,
+ STAGE_RERUN) = range(32, 40)
 
 # every symbol include/sgm.h declares
 EXPORTS = ("sgm_default_params", "sgm_paper_params", "sgm_create", "sgm_destroy", "sgm_full_frame", "sgm_reduced_frame",

@@ -537,6 +537,7 @@ int sgm_create(const sgm_params *prm, sgm_context **out)
     A(hipMemset(b.sflags, 0, N));
     A(hipMemset(b.mask, 0, N));
     A(hipMemset(b.flags, 0, N));
+    A(hipMemset(b.rerun, 0, RR_WORDS * sizeof(uint32_t)));
     A(hipMemset(b.dhat, 0, N * sizeof(double)));
     A(hipMemset(b.pm, 0, N * sizeof(double)));
     A(hipMemset(b.off, 0, (N + 1) * sizeof(uint32_t)));
@@ -869,6 +870,12 @@ int sgm_get_stage(sgm_context *ctx, int32_t stage, void *out, size_t bytes, void
               : stage == SGM_STAGE_CNN_OUT ? (const void *)b.cnn_out
               : stage == SGM_STAGE_HALFWIDTH ? (const void *)b.hw : (const void *)b.rpix;
         need = stage == SGM_STAGE_FEATURES || stage == SGM_STAGE_CNN_OUT ? N * 8 : N * 4;
+        break;
+    case SGM_STAGE_RERUN:
+        if (!ctx->prm.gate_rerun)
+            return fail(SGM_EINVAL, "SGM_STAGE_RERUN exists in gate_rerun contexts only");
+        src = b.rerun;   // RR_NW, RR_NMOVED, RR_EXTRA
+        need = 3 * sizeof(uint32_t);
         break;
     case SGM_STAGE_KAPPA:
         if (!(ctx->prm.r_curv > 0))

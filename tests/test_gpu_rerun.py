@@ -73,7 +73,13 @@ def _compare_routes(seq, D, frames=(1, 2, 3), label="", model=None, extra=(), **
         for name in ("sparse", "fallback"):
             for key, v in ref.items():
                 assert np.array_equal(outs[name][key], v), (D, label, k, name, key)
-        failed += int(((ref["flags"] & NAT.FLAG_GATEFAIL) != 0).sum())
+        nfail = int(((ref["flags"] & NAT.FLAG_GATEFAIL) != 0).sum())
+        # the device-side counts: widened = GATEFAIL pixels, moved <= widened,
+        # added cells <= widened * (D - 1); equal on every route
+        counts = [_np(g.stage(NAT.STAGE_RERUN)).tolist() for g in ctx.values()]
+        assert counts[0][0] == nfail and counts[0][1] <= nfail and counts[0][2] <= nfail * (D - 1), counts
+        assert counts[1] == counts[0] and counts[2] == counts[0], counts
+        failed += nfail
     _say(f"  widened pixels: {failed} of {len(frames) * W * H}")
     return failed, ctx
 
