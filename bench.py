@@ -266,7 +266,7 @@ def main():
     g = sgmk.ReducedSGM(W, H, D, **params)
     g.full_frame(Ls[0], Rs[0])
     cells = []
-    bad_d, bad_z, nval = 0, 0, 0
+    bad_d, bad_z, kit_d, nval = 0, 0, 0, 0
     for i, ((a, b), T) in enumerate(zip(sched, Ts)):
         g.reduced_frame(Ls[b], Rs[b], T)
         cells.append(g.cost_cells())
@@ -275,8 +275,10 @@ def main():
             gt = torch.from_numpy(seq.disp_gt[b].astype(np.float32)).to(dev)
             d = g.disparity()
             dz = g.stage(sgmk.N.STAGE_DZ).float()
-            bad_d += int(((d - gt).abs() > 3)[v].sum())
+            err = (d - gt).abs()
+            bad_d += int((err > 3)[v].sum())
             bad_z += int(((dz - gt).abs() > 3)[v].sum())
+            kit_d += int(((err > 3) & (err > 0.05 * gt))[v].sum())   # KITTI: > 3 px and > 5 %
             nval += int(v.sum())
     timed_cells = sum(cells[args.warmup:])
     g.close()
@@ -334,17 +336,20 @@ def main():
         for i in range(args.full_steps):
             gf.full_frame(Ls[i % seq.frames], Rs[i % seq.frames])
         full_stage_ms, nf = gf.read_profile()
-        full_bad = 0
+        full_bad, full_kit = 0, 0
         for k in range(1, seq.frames):
             gf.full_frame(Ls[k], Rs[k])
             v = torch.from_numpy(seq.valid[k]).to(dev)
             gt = torch.from_numpy(seq.disp_gt[k].astype(np.float32)).to(dev)
-            full_bad += int(((gf.disparity() - gt).abs() > 3)[v].sum())
+            err = (gf.disparity() - gt).abs()
+            full_bad += int((err > 3)[v].sum())
+            full_kit += int(((err > 3) & (err > 0.05 * gt))[v].sum())
         gf.close()
         full = {"frames_per_s": round(full_fps, 2), "ms_per_frame": round(dtf / args.full_steps * 1e3, 4),
                 "cost_cells_per_s": round(full_fps * H * W * D, 1),
                 "stage_ms": {k: round(v / max(nf, 1), 5) for k, v in full_stage_ms.items()},
-                "bad_px_gt3": round(full_bad / max(nval, 1), 6)}
+                "bad_px_gt3": round(full_bad / max(nval, 1), 6),
+                "bad_px_kitti": round(full_kit / max(nval, 1), 6)}
 
     # ---- roofline of the dominant kernel ---------------------------------
     mean_cells = timed_cells / args.steps
@@ -382,6 +387,9 @@ def main():
         "ms_per_step_with_events": round(dt_prof / args.steps * 1e3, 4),
         "bad_px_gt3": {"reduced_d": round(bad_d / max(nval, 1), 6), "reduced_dz": round(bad_z / max(nval, 1), 6),
                        "full_range": full["bad_px_gt3"] if full else None, "frames": "1-19"},
+        "bad_px_kitti": {"reduced_d": round(kit_d / max(nval, 1), 6),
+                         "full_range": full["bad_px_kitti"] if full else None,
+                         "definition": "error > 3 px and > 5 % of the true disparity", "frames": "1-19"},
         "roofline": roofline,
         "post": post,
     }
