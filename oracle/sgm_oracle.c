@@ -423,7 +423,7 @@ int orc_predict_aux(const orc_params *prm, const double *d, const double *p, con
         }
     }
     /* discontinuity rejection, decided on the filled map before any pixel is
-     * rejected (has[] is reused to hold the verdict) */
+     * rejected (has[] is reused to hold the decision) */
     for (int y = 0; y < H; y++) {
         for (int x = 0; x < W; x++) {
             int t = y * W + x;
