@@ -2024,7 +2024,7 @@ struct WalkArgs {
     const uint32_t *skip;
 };
 
-constexpr int RW_T = 256;   // four waves per block, one scanline each
+constexpr int RW_T = 64;   // one wave (one scanline) per block: a finished scanline frees its slot at once
 
 // Eq. 1 at one pixel for a whole wave (lanes by disparity, chunk j holds
 // d = 64 j + lane): Ln = LBIG outside the window [lo, hi]
