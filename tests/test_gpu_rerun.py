@@ -127,6 +127,15 @@ def test_sparse_rerun_path_subsets(mask):
         g.close()
 
 
+def test_sparse_rerun_tall_image():
+    # taller than wide: most diagonal scanlines enter through the side borders
+    seq = synth.make_sequence("tiny", frames=3, width=40, height=120, seed=5)
+    failed, ctx = _compare_routes(seq, 32, frames=(1, 2), label="40x120", chi2_gate=0.5)
+    assert failed > 0
+    for g in ctx.values():
+        g.close()
+
+
 def test_sparse_rerun_small_image():
     # scanlines shorter than one 64-pixel batch, and more disparities than columns
     seq = synth.make_sequence("tiny", frames=3, width=37, height=19, seed=3)
